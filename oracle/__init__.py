@@ -1,0 +1,245 @@
+"""FP64 CPU oracle of the thermal LBM step with Hermite body force (ctypes shim).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+library (the HIP path) never imports, links or calls it, and this package never
+imports the product package.  The C source derives its own quadrature rule and
+Hermite tensors; see the header of ``lbm_oracle.c`` for what each function
+follows in the paper (Li & Shan, arXiv:2302.04741, Sec. 2: eqs. (fN), (F),
+(f3), (fi), (lbm) and the mid-point stress).
+
+Layouts used here (the oracle's own; they need not match the GPU library):
+  * fields are SoA numpy arrays: rho (N,), u (D, N), theta (N,), g (D, N);
+  * populations are AoS: f (N, Q), cell = (z*ny + y)*nx + x;
+  * the body force is always a full (D, N) field; ``g_uniform`` and
+    ``g_axis_profile`` expand the two other force kinds into one.
+
+Force orders: 1 = first Hermite term only, 2 = up to the second (the
+Guo-equivalent scheme, "without a3_F"), 3 = up to the third without the stress
+term, 4 = up to the third including sigma-bar (the full scheme).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+D2Q37 = 0
+D3Q39 = 1
+DIM = {D2Q37: 2, D3Q39: 3}
+
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_int = ctypes.c_int
+_ptr = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.oracle_lattice.argtypes = [_int, _ptr, _ptr, _ptr, _ptr]
+        L.oracle_hermite.argtypes = [_int, _int, _ptr]
+        L.oracle_maxwell_coeff.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr]
+        L.oracle_equilibrium.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr]
+        L.oracle_force.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr, _ptr, _ptr]
+        L.oracle_init.argtypes = [_int, _i64, _i64, _i64, _int, _int,
+                                  _ptr, _ptr, _ptr, _ptr, _ptr, _int]
+        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, _dbl, _int, _int,
+                                  _ptr, _ptr, _ptr, _i64, _int]
+        L.oracle_moments.argtypes = [_int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _int]
+        L.oracle_sigma.argtypes = [_int, _i64, _dbl, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_heat_flux.argtypes = [_int, _i64, _dbl, _int, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_totals.argtypes = [_int, _i64, _ptr, _ptr]
+        L.oracle_num_threads.argtypes = [_int]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "float64 C-contiguous expected"
+    return a.ctypes.data_as(_ptr)
+
+
+def _vec(v, D):
+    out = np.zeros(3)
+    out[:D] = np.asarray(v, dtype=np.float64)[:D]
+    return out
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ValueError("oracle %s failed with code %d" % (what, rc))
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# Lattice and per-cell pieces
+# ---------------------------------------------------------------------------
+
+def lattice(lat: int):
+    """Return (c (Q,3) int, w (Q,), r, degree) as derived by the oracle."""
+    c = np.zeros((64, 3), dtype=np.int32)
+    w = np.zeros(64)
+    r = _dbl()
+    d = _int()
+    Q = _check(lib().oracle_lattice(lat, c.ctypes.data_as(_ptr), _p(w), ctypes.byref(r),
+                                    ctypes.byref(d)), "lattice")
+    return c[:Q].copy(), w[:Q].copy(), r.value, d.value
+
+
+def velocities(lat: int) -> np.ndarray:
+    c, _, r, _ = lattice(lat)
+    return r * c[:, :DIM[lat]].astype(np.float64)
+
+
+def hermite(lat: int, n: int) -> np.ndarray:
+    """H^(n)(xi_i) for every velocity, shape (Q,) + (D,)*n."""
+    c, _, _, _ = lattice(lat)
+    D = DIM[lat]
+    out = np.zeros(len(c) * D ** n)
+    _check(lib().oracle_hermite(lat, n, _p(out)), "hermite")
+    return out.reshape((len(c),) + (D,) * n)
+
+
+def maxwell_coeff(D: int, n: int, rho: float, u, theta: float) -> np.ndarray:
+    out = np.zeros(D ** n)
+    _check(lib().oracle_maxwell_coeff(D, n, rho, _p(_vec(u, D)), theta, _p(out)),
+           "maxwell_coeff")
+    return out.reshape((D,) * n)
+
+
+def equilibrium(lat: int, rho: float, u, theta: float, eq_order: int = 0) -> np.ndarray:
+    Q = len(lattice(lat)[0])
+    out = np.zeros(Q)
+    _check(lib().oracle_equilibrium(lat, eq_order, rho, _p(_vec(u, DIM[lat])), theta,
+                                    _p(out)), "equilibrium")
+    return out
+
+
+def force(lat: int, force_order: int, rho: float, u, theta: float, g, sigma=None) -> np.ndarray:
+    D = DIM[lat]
+    Q = len(lattice(lat)[0])
+    sig = np.zeros(9)
+    if sigma is not None:
+        sig[:D * D] = np.asarray(sigma, dtype=np.float64).reshape(D * D)
+    out = np.zeros(Q)
+    _check(lib().oracle_force(lat, force_order, rho, _p(_vec(u, D)), theta, _p(_vec(g, D)),
+                              _p(sig), _p(out)), "force")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Force fields
+# ---------------------------------------------------------------------------
+
+def g_uniform(D: int, ncell: int, g) -> np.ndarray:
+    g = np.asarray(g, dtype=np.float64)[:D]
+    return np.ascontiguousarray(np.repeat(g[:, None], ncell, axis=1))
+
+
+def g_axis_profile(D: int, dims, axis: int, prof) -> np.ndarray:
+    """prof: (D, L_axis) acceleration as a function of the coordinate along `axis`
+    (0 = x, 1 = y, 2 = z); dims = (nx, ny, nz)."""
+    nx, ny, nz = dims
+    prof = np.asarray(prof, dtype=np.float64).reshape(D, -1)
+    idx = np.indices((nz, ny, nx))  # z, y, x
+    coord = idx[2 - axis].reshape(-1)
+    return np.ascontiguousarray(prof[:, coord])
+
+
+# ---------------------------------------------------------------------------
+# Simulation
+# ---------------------------------------------------------------------------
+
+class OracleSim:
+    """A periodic grid of stored populations advanced by the oracle's step."""
+
+    def __init__(self, lat: int, dims, tau_hat: float, rho, u, theta, g,
+                 eq_order: int = 0, force_order: int = 4, nthreads: int = 0):
+        self.lat = lat
+        self.D = DIM[lat]
+        nx, ny, nz = (tuple(dims) + (1, 1))[:3]
+        self.dims = (int(nx), int(ny), int(nz))
+        self.N = nx * ny * nz
+        self.Q = len(lattice(lat)[0])
+        self.tau_hat = float(tau_hat)
+        self.eq_order = eq_order
+        self.force_order = force_order
+        self.nthreads = nthreads
+        N, D = self.N, self.D
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), (N,)))
+        u = np.ascontiguousarray(np.asarray(u, np.float64).reshape(D, N))
+        theta = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, np.float64), (N,)))
+        self.set_force(g)
+        self.f = np.zeros((N, self.Q))
+        self._tmp = np.zeros_like(self.f)
+        _check(lib().oracle_init(lat, *self.dims, eq_order, force_order, _p(rho), _p(u),
+                                 _p(theta), _p(self.g), _p(self.f), nthreads), "init")
+        self.time = 0
+
+    def set_force(self, g):
+        g = np.asarray(g, dtype=np.float64)
+        if g.ndim == 1:
+            g = g_uniform(self.D, self.N, g)
+        self.g = np.ascontiguousarray(g.reshape(self.D, self.N))
+
+    def step(self, n: int = 1):
+        _check(lib().oracle_step(self.lat, *self.dims, self.tau_hat, self.eq_order,
+                                 self.force_order, _p(self.g), _p(self.f), _p(self._tmp),
+                                 int(n), self.nthreads), "step")
+        self.time += int(n)
+
+    def moments(self):
+        N, D = self.N, self.D
+        rho, u, th = np.zeros(N), np.zeros((D, N)), np.zeros(N)
+        _check(lib().oracle_moments(self.lat, N, _p(self.f), _p(self.g), _p(rho), _p(u),
+                                    _p(th), self.nthreads), "moments")
+        return rho, u, th
+
+    def sigma(self):
+        N, D = self.N, self.D
+        s = np.zeros((D, D, N))
+        _check(lib().oracle_sigma(self.lat, N, self.tau_hat, self.eq_order, _p(self.f),
+                                  _p(self.g), _p(s), self.nthreads), "sigma")
+        return s
+
+    def heat_flux(self):
+        N, D = self.N, self.D
+        q = np.zeros((D, N))
+        _check(lib().oracle_heat_flux(self.lat, N, self.tau_hat, self.eq_order,
+                                      self.force_order, _p(self.f), _p(self.g), _p(q),
+                                      self.nthreads), "heat_flux")
+        return q
+
+    def totals(self):
+        out = np.zeros(2 + self.D)
+        _check(lib().oracle_totals(self.lat, self.N, _p(self.f), _p(out)), "totals")
+        return out
+
+
+def num_threads(n: int = 0) -> int:
+    return lib().oracle_num_threads(n)

@@ -1,0 +1,55 @@
+"""The seeded input generators (host-only, no method arithmetic)."""
+import math
+
+import numpy as np
+
+from paper_2302_04741_amd import workloads
+
+
+def test_kolmogorov_modes_half_space():
+    ks = workloads.kolmogorov_modes()
+    assert len(ks) == 62
+    s = {tuple(k) for k in ks}
+    assert all(tuple(-k) not in s for k in ks)
+    assert np.abs(ks).max() == 2
+
+
+def test_kolmogorov_perturbation_matches_direct_sum():
+    n = 16
+    wl = workloads.kolmogorov_3d(n=n)
+    ks = workloads.kolmogorov_modes()
+    phi = np.random.default_rng(workloads.KOLMOGOROV_SEED).uniform(0, 2 * math.pi, (3, 62))
+    A = 1e-3 * math.sqrt(2 / 62)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        x, y, z = rng.integers(0, n, 3)
+        cell = (z * n + y) * n + x
+        for a in range(3):
+            ref = A * sum(math.sin(2 * math.pi * (k[0] * x + k[1] * y + k[2] * z) / n + phi[a, m])
+                          for m, k in enumerate(ks))
+            assert abs(wl.u[a, cell] - ref) < 1e-17
+    # each component has RMS equal to the stated amplitude
+    np.testing.assert_allclose(np.sqrt((wl.u ** 2).mean(axis=1)), 1e-3, rtol=1e-12)
+    g = wl.force_field()
+    z = np.arange(n ** 3) // (n * n)
+    np.testing.assert_allclose(g[0], 1e-5 * np.sin(2 * math.pi * z / n), atol=1e-20)
+    assert np.all(g[1:] == 0)
+
+
+def test_parity_workload_fields():
+    wl = workloads.periodic_2d()
+    assert wl.dims == (64, 64, 1) and wl.tau_hat == 0.8 and wl.steps == 1000
+    x = np.arange(64 * 64) % 64
+    y = np.arange(64 * 64) // 64
+    np.testing.assert_allclose(wl.rho, 1 + 0.01 * np.sin(2 * math.pi * x / 64))
+    np.testing.assert_allclose(wl.theta, 1 + 0.05 * np.sin(2 * math.pi * y / 64))
+    assert np.all(wl.u == 0)
+
+
+def test_shear_workload_fields():
+    wl = workloads.thermal_shear_2d(n=32, dtheta=0.1, mach=0.2)
+    y = np.arange(32 * 32) // 32
+    s = np.sin(2 * math.pi * y / 32)
+    np.testing.assert_allclose(wl.theta, 1 + 0.1 * s)
+    np.testing.assert_allclose(wl.u[0], 0.2 * np.sqrt(1 + 0.1 * s) * s)
+    assert np.all(wl.u[1] == 0) and np.all(wl.rho == 1)
