@@ -1,0 +1,200 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) thermal lattice Boltzmann library.
+ *
+ * The library advances the discrete populations of a high-order thermal
+ * lattice Boltzmann model with a body force, following Li & Shan, "Body-force
+ * modelling in thermal compressible flows with lattice Boltzmann method"
+ * (arXiv:2302.04741):
+ *   - velocity sets: D2Q37 (degree-9 Gauss-Hermite rule, Sec. 3) and D3Q39
+ *     (degree-7 rule, same construction as Sec. 2);
+ *   - equilibrium: the Hermite expansion of the Maxwellian to order N,
+ *     eq. (fN) with the coefficients a_0^(n) of Sec. 2 (N = 4 on D2Q37,
+ *     N = 3 on D3Q39 by default);
+ *   - body force: the Hermite expansion eq. (F), up to the third moment
+ *     including the non-equilibrium stress, eq. (fi);
+ *   - time step: eq. (lbm) with second-order time treatment: equilibrium and
+ *     force evaluated at the mid-point values rho, u + g/2, theta and the
+ *     mid-point stress sigma-bar of Sec. 2; BGK relaxation time tau-hat.
+ * One step is one fused GPU kernel: pull streaming, moments, equilibrium,
+ * stress, force, relaxation and the write of the new populations.
+ *
+ * Units: velocities in units of sqrt(theta_0) (theta_0 = 1), time in steps,
+ * lengths in lattice nodes; g is the velocity increment per step.  Every grid
+ * is periodic in every axis.
+ *
+ * Memory: the caller owns all device memory.  The library never allocates or
+ * frees device memory: the state lives in a caller-provided workspace of
+ * lbm_workspace_bytes() bytes.  Every call that takes device pointers runs
+ * asynchronously on the handle's HIP stream, except lbm_totals, which
+ * synchronises that stream to return host values.
+ *
+ * Errors: calls return an lbm_status; argument errors are detected
+ * synchronously, before any GPU work is queued, and leave the handle
+ * unchanged.  lbm_last_error() returns a thread-local message for the last
+ * failure on the calling thread.  A handle is not thread-safe; distinct
+ * handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_sim lbm_sim; /* opaque host handle */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad value) */
+    LBM_EUNSUPPORTED = -2, /* valid request this build does not implement */
+    LBM_EDEVICE = -3,      /* a HIP call failed; see lbm_last_error() */
+    LBM_ENOSPACE = -4,     /* workspace too small */
+    LBM_ENONFINITE = -5    /* a global total is NaN or infinite (diverged run) */
+} lbm_status;
+
+typedef enum { LBM_D2Q37 = 0, LBM_D3Q39 = 1 } lbm_lattice;
+
+/* Population storage.  Arithmetic runs in FP64 for LBM_F64 and FP32 for
+ * LBM_F32 and LBM_F16DEV.  Every storage type holds h_i = f~_i - w_i rho0
+ * (see lbm_params.rho0); LBM_F16DEV stores h_i scaled by 2^k_i, k_i =
+ * round(-log2 w_i), as IEEE half, so that deviations stay normal numbers. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
+
+/* Truncation of the force expansion eq. (F).  The paper's N = 0, 1, 2 are
+ * orders 1, 2, 3 here; "N = 2 without sigma" is LBM_FORCE_N2_NOSIGMA.
+ * LBM_FORCE_N1_GUO keeps the first two moments only (Guo's scheme, i.e. the
+ * force without a3_F). */
+typedef enum {
+    LBM_FORCE_N0 = 1,
+    LBM_FORCE_N1_GUO = 2,
+    LBM_FORCE_N2_NOSIGMA = 3,
+    LBM_FORCE_N2 = 4
+} lbm_force_order;
+
+typedef enum { LBM_G_UNIFORM = 0, LBM_G_AXIS_PROFILE = 1, LBM_G_FIELD = 2 } lbm_force_kind;
+
+/* lbm_params.flags */
+#define LBM_FLAG_FORCE_FIELD 1u /* reserve workspace for an LBM_G_FIELD force */
+
+typedef struct {
+    uint32_t struct_size; /* = sizeof(lbm_params); ABI versioning */
+    int32_t lattice;      /* lbm_lattice */
+    int32_t storage;      /* lbm_storage */
+    int32_t eq_order;     /* 0 = highest the rule supports (4 D2Q37, 3 D3Q39); else 2..that */
+    int32_t force_order;  /* lbm_force_order; LBM_FORCE_N2 is the full scheme */
+    uint32_t flags;       /* LBM_FLAG_* */
+    int64_t nx, ny, nz;   /* grid extents, >= 1; nz == 1 for D2Q37; ny, nz <= 65535 */
+    double tau_hat;       /* relaxation time of eq. (lbm), tau-hat = tau + 1/2; > 0.5 */
+    double rho0;          /* reference density, >= 0: populations are stored and
+                             advanced as deviations h_i = f~_i - w_i rho0.  rho0 = 1
+                             keeps every stored value and every rounding at the size
+                             of the deviations; rho0 = 0 stores f~ itself (the
+                             literal form of eq. (lbm)). */
+} lbm_params;
+
+/* Bytes of device workspace a handle needs for these parameters (256-byte
+ * aligned sub-buffers included).  Returns 0 if the parameters are invalid. */
+LBM_API size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Create a handle and initialise the populations from FP64 device fields.
+ *   workspace : device memory of >= lbm_workspace_bytes(p) bytes, 256-byte
+ *               aligned, owned by the caller, not freed by the library; it
+ *               must stay valid until lbm_destroy.
+ *   hip_stream: the hipStream_t every call of this handle runs on (NULL = the
+ *               null stream).
+ *   rho, theta: N = nx*ny*nz doubles; u: D*N doubles (component-major, u[a*N +
+ *               cell]); cell = (z*ny + y)*nx + x.  Read by an init kernel queued
+ *               on hip_stream: the caller may reuse them once that stream
+ *               has passed this call.
+ * The initial stored state is f~ = f0(rho, u, theta) - F/2 with the current
+ * force (zero until lbm_set_force), so lbm_moments reports exactly the inputs
+ * at step 0.  Returns LBM_EINVAL / LBM_EUNSUPPORTED / LBM_ENOSPACE without
+ * queuing work, LBM_EDEVICE if the launch fails. */
+LBM_API lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_bytes,
+                      void *hip_stream, const double *rho, const double *u,
+                      const double *theta, lbm_sim **out);
+
+/* Set the body acceleration g (Sec. 2, eq. (BGK): the acceleration of the body
+ * force).  kind:
+ *   LBM_G_UNIFORM      g: D host doubles; axis and len ignored.
+ *   LBM_G_AXIS_PROFILE g: D*len device doubles, g[a*len + k] = g_a at
+ *                      coordinate k along `axis` (0 = x, 1 = y, 2 = z);
+ *                      len must equal that grid extent.
+ *   LBM_G_FIELD        g: D*N device doubles, g[a*N + cell]; needs
+ *                      LBM_FLAG_FORCE_FIELD at creation.
+ * Device data are copied (and converted to the arithmetic precision) into the
+ * workspace on the handle's stream; the caller may reuse them afterwards.
+ * Before the first step the stored state is rebuilt from its moments so that
+ * f~ = f0 - F/2 holds with the new g (the moments reported at step 0 stay the
+ * initial ones); after that, g applies from the next step on. */
+LBM_API lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis, int64_t len);
+
+/* Advance nsteps (>= 0) time steps of eq. (lbm); asynchronous. */
+LBM_API lbm_status lbm_step(lbm_sim *s, int64_t nsteps);
+
+/* Physical moments at the current step, eq. (rut1) with the mid-point shift:
+ * rho, u = u~ + g/2 and theta (the mid-point values of Sec. 2).  Device FP64
+ * outputs: rho[N], u[D*N] (component-major), theta[N]; any may be NULL. */
+LBM_API lbm_status lbm_moments(lbm_sim *s, double *rho, double *u, double *theta);
+
+/* Destroy the handle (NULL is a no-op).  Does not free the workspace and does
+ * not wait for queued work; the workspace may be reused once the stream has
+ * drained. */
+LBM_API void lbm_destroy(lbm_sim *s);
+
+/* Thread-local message of the last failed call ("" if none). */
+LBM_API const char *lbm_last_error(void);
+
+/* ---- diagnostics, checkpointing and tables (not part of the step path) ---- */
+
+/* Global sums over the grid of the stored populations, reduced in FP64 in a
+ * fixed order (bitwise reproducible):
+ * out[0] = sum f~, out[1..D] = sum f~ xi_a, out[D+1] = sum f~ |xi|^2 (host,
+ * D+2 doubles).  Synchronises the handle's stream.  Returns LBM_ENONFINITE if
+ * any sum is not finite. */
+LBM_API lbm_status lbm_totals(lbm_sim *s, double *out);
+
+/* Heat flux q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical
+ * distribution f = f0 + (1 - 1/(2 tau-hat)) (f~ - f0 + F/2) at the current
+ * step (the quantity q_err of Sec. 2 refers to).  q: D*N device doubles. */
+LBM_API lbm_status lbm_heat_flux(lbm_sim *s, double *q);
+
+/* Raw population storage (lbm_population_bytes bytes, library layout: SoA
+ * planes of h_i in the storage type, post-collision "pull" layout) for
+ * checkpoint/restart: get copies out, set copies in (device buffers, async).
+ * Restoring a state together with lbm_set_step_count resumes bitwise. */
+LBM_API size_t lbm_population_bytes(const lbm_sim *s);
+LBM_API lbm_status lbm_get_populations(lbm_sim *s, void *dst);
+LBM_API lbm_status lbm_set_populations(lbm_sim *s, const void *src);
+LBM_API int64_t lbm_step_count(const lbm_sim *s);
+LBM_API lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
+
+/* Change the stream of a handle (work already queued stays where it is). */
+LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
+
+/* Kernel launch shape of the step: threads per block along x (64, 128, 256,
+ * 512 or 1024).  0 restores the default.  Results do not depend on it. */
+LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
+
+/* The velocity set compiled into the library (host call, no GPU needed):
+ * c: Q*3 ints, w: Q doubles, r: the scale with xi_i = r c_i.  Returns Q, or a
+ * negative lbm_status. */
+LBM_API int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r);
+
+/* Library version string. */
+LBM_API const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -14,6 +14,11 @@ Layouts used here (the oracle's own; they need not match the GPU library):
   * the body force is always a full (D, N) field; ``g_uniform`` and
     ``g_axis_profile`` expand the two other force kinds into one.
 
+Precision: ``prec="f64"`` (the oracle proper, binary64) or ``prec="ld"``, the
+same source built with x87 80-bit long double.  The 80-bit build exists only to
+measure how far the binary64 oracle itself drifts from a more precise run of
+the same algorithm (its rounding floor); parity claims are against "f64".
+
 Force orders: 1 = first Hermite term only, 2 = up to the second (the
 Guo-equivalent scheme, "without a3_F"), 3 = up to the third without the stress
 term, 4 = up to the third including sigma-bar (the full scheme).
@@ -28,7 +33,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIBS = {"f64": os.path.join(_HERE, "liboracle.so"),
+         "ld": os.path.join(_HERE, "liboracle_ld.so")}
+_DTYPE = {"f64": np.float64, "ld": np.longdouble}
+_CREAL = {"f64": ctypes.c_double, "ld": ctypes.c_longdouble}
 
 D2Q37 = 0
 D3Q39 = 1
@@ -41,46 +49,50 @@ _ptr = ctypes.c_void_p
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
-               "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (no FMA contraction, no fast-math): the
+    binary64 build and the 80-bit build of the same source."""
+    for prec, path in _LIBS.items():
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp%d" % os.getpid()
+            cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                   "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+            if prec == "ld":
+                cmd.insert(1, "-DOR_REAL=long double")
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, path)
+    return _LIBS["f64"]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(prec: str = "f64"):
+    if prec not in _libs:
+        path = _LIBS[prec]
+        if not os.path.exists(path):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
+        R = _CREAL[prec]
         L.oracle_lattice.argtypes = [_int, _ptr, _ptr, _ptr, _ptr]
         L.oracle_hermite.argtypes = [_int, _int, _ptr]
-        L.oracle_maxwell_coeff.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr]
-        L.oracle_equilibrium.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr]
-        L.oracle_force.argtypes = [_int, _int, _dbl, _ptr, _dbl, _ptr, _ptr, _ptr]
+        L.oracle_maxwell_coeff.argtypes = [_int, _int, R, _ptr, R, _ptr]
+        L.oracle_equilibrium.argtypes = [_int, _int, R, _ptr, R, _ptr]
+        L.oracle_force.argtypes = [_int, _int, R, _ptr, R, _ptr, _ptr, _ptr]
         L.oracle_init.argtypes = [_int, _i64, _i64, _i64, _int, _int,
                                   _ptr, _ptr, _ptr, _ptr, _ptr, _int]
-        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, _dbl, _int, _int,
+        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, R, _int, _int,
                                   _ptr, _ptr, _ptr, _i64, _int]
         L.oracle_moments.argtypes = [_int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _int]
-        L.oracle_sigma.argtypes = [_int, _i64, _dbl, _int, _ptr, _ptr, _ptr, _int]
-        L.oracle_heat_flux.argtypes = [_int, _i64, _dbl, _int, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_sigma.argtypes = [_int, _i64, R, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_heat_flux.argtypes = [_int, _i64, R, _int, _int, _ptr, _ptr, _ptr, _int]
         L.oracle_totals.argtypes = [_int, _i64, _ptr, _ptr]
         L.oracle_num_threads.argtypes = [_int]
-        _lib = L
-    return _lib
+        _libs[prec] = L
+    return _libs[prec]
 
 
 def _p(a: np.ndarray):
-    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "float64 C-contiguous expected"
+    assert a.dtype in (np.float64, np.longdouble) and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_ptr)
 
 
@@ -179,9 +191,13 @@ class OracleSim:
     """A periodic grid of stored populations advanced by the oracle's step."""
 
     def __init__(self, lat: int, dims, tau_hat: float, rho, u, theta, g,
-                 eq_order: int = 0, force_order: int = 4, nthreads: int = 0):
+                 eq_order: int = 0, force_order: int = 4, nthreads: int = 0,
+                 prec: str = "f64"):
         self.lat = lat
         self.D = DIM[lat]
+        self.prec = prec
+        self.dt = _DTYPE[prec]
+        self.L = lib(prec)
         nx, ny, nz = (tuple(dims) + (1, 1))[:3]
         self.dims = (int(nx), int(ny), int(nz))
         self.N = nx * ny * nz
@@ -190,56 +206,57 @@ class OracleSim:
         self.eq_order = eq_order
         self.force_order = force_order
         self.nthreads = nthreads
-        N, D = self.N, self.D
-        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), (N,)))
-        u = np.ascontiguousarray(np.asarray(u, np.float64).reshape(D, N))
-        theta = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, np.float64), (N,)))
+        N, D, dt = self.N, self.D, self.dt
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dt), (N,)))
+        u = np.ascontiguousarray(np.asarray(u, dt).reshape(D, N))
+        theta = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, dt), (N,)))
         self.set_force(g)
-        self.f = np.zeros((N, self.Q))
+        self.f = np.zeros((N, self.Q), dtype=dt)
         self._tmp = np.zeros_like(self.f)
-        _check(lib().oracle_init(lat, *self.dims, eq_order, force_order, _p(rho), _p(u),
-                                 _p(theta), _p(self.g), _p(self.f), nthreads), "init")
+        _check(self.L.oracle_init(lat, *self.dims, eq_order, force_order, _p(rho), _p(u),
+                                  _p(theta), _p(self.g), _p(self.f), nthreads), "init")
         self.time = 0
 
     def set_force(self, g):
         g = np.asarray(g, dtype=np.float64)
         if g.ndim == 1:
             g = g_uniform(self.D, self.N, g)
-        self.g = np.ascontiguousarray(g.reshape(self.D, self.N))
+        self.g = np.ascontiguousarray(g.reshape(self.D, self.N).astype(self.dt))
 
     def step(self, n: int = 1):
-        _check(lib().oracle_step(self.lat, *self.dims, self.tau_hat, self.eq_order,
-                                 self.force_order, _p(self.g), _p(self.f), _p(self._tmp),
-                                 int(n), self.nthreads), "step")
+        _check(self.L.oracle_step(self.lat, *self.dims, self.tau_hat, self.eq_order,
+                                  self.force_order, _p(self.g), _p(self.f), _p(self._tmp),
+                                  int(n), self.nthreads), "step")
         self.time += int(n)
 
     def moments(self):
-        N, D = self.N, self.D
-        rho, u, th = np.zeros(N), np.zeros((D, N)), np.zeros(N)
-        _check(lib().oracle_moments(self.lat, N, _p(self.f), _p(self.g), _p(rho), _p(u),
-                                    _p(th), self.nthreads), "moments")
-        return rho, u, th
+        """(rho, u, theta) as float64 arrays (rounded from the working precision)."""
+        N, D, dt = self.N, self.D, self.dt
+        rho, u, th = np.zeros(N, dt), np.zeros((D, N), dt), np.zeros(N, dt)
+        _check(self.L.oracle_moments(self.lat, N, _p(self.f), _p(self.g), _p(rho), _p(u),
+                                     _p(th), self.nthreads), "moments")
+        return rho.astype(np.float64), u.astype(np.float64), th.astype(np.float64)
 
     def sigma(self):
         N, D = self.N, self.D
-        s = np.zeros((D, D, N))
-        _check(lib().oracle_sigma(self.lat, N, self.tau_hat, self.eq_order, _p(self.f),
-                                  _p(self.g), _p(s), self.nthreads), "sigma")
-        return s
+        s = np.zeros((D, D, N), self.dt)
+        _check(self.L.oracle_sigma(self.lat, N, self.tau_hat, self.eq_order, _p(self.f),
+                                   _p(self.g), _p(s), self.nthreads), "sigma")
+        return s.astype(np.float64)
 
     def heat_flux(self):
         N, D = self.N, self.D
-        q = np.zeros((D, N))
-        _check(lib().oracle_heat_flux(self.lat, N, self.tau_hat, self.eq_order,
-                                      self.force_order, _p(self.f), _p(self.g), _p(q),
-                                      self.nthreads), "heat_flux")
-        return q
+        q = np.zeros((D, N), self.dt)
+        _check(self.L.oracle_heat_flux(self.lat, N, self.tau_hat, self.eq_order,
+                                       self.force_order, _p(self.f), _p(self.g), _p(q),
+                                       self.nthreads), "heat_flux")
+        return q.astype(np.float64)
 
     def totals(self):
-        out = np.zeros(2 + self.D)
-        _check(lib().oracle_totals(self.lat, self.N, _p(self.f), _p(out)), "totals")
-        return out
+        out = np.zeros(2 + self.D, self.dt)
+        _check(self.L.oracle_totals(self.lat, self.N, _p(self.f), _p(out)), "totals")
+        return out.astype(np.float64)
 
 
-def num_threads(n: int = 0) -> int:
-    return lib().oracle_num_threads(n)
+def num_threads(n: int = 0, prec: str = "f64") -> int:
+    return lib(prec).oracle_num_threads(n)

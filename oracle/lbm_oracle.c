@@ -9,8 +9,8 @@
  * the GPU path: it derives its own quadrature rule, builds its own Hermite tensors
  * and works on its own data layout (populations per cell, AoS; push streaming).
  *
- * Everything is IEEE binary64, round-to-nearest, built without FMA contraction
- * (-ffp-contract=off) and without fast-math.  Cells are independent within a
+ * Everything is IEEE binary64 (type `real`), round-to-nearest, built without
+ * FMA contraction (-ffp-contract=off) and without fast-math.  Cells are independent within a
  * step, so the OpenMP loop over cells does not change any result; cross-cell
  * sums (totals) run serially in a fixed order.
  *
@@ -48,6 +48,14 @@
 #include <omp.h>
 #endif
 
+/* Working precision: binary64 by default.  The same source built with
+ * -DOR_REAL="long double" gives an 80-bit build, used by the tests only to
+ * measure the rounding floor of the binary64 build. */
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+typedef OR_REAL real;
+
 #define OR_MAXQ 64
 #define OR_NMAX 4   /* highest Hermite order held (equilibrium up to 4) */
 #define OR_TMAX 81  /* 3^4 components of a rank-4 tensor in 3-D */
@@ -58,10 +66,10 @@ typedef struct {
     int ok;
     int D, Q, degree, max_eq_order;
     int c[OR_MAXQ][3];
-    double w[OR_MAXQ];
-    double r;
-    double xi[OR_MAXQ][3];
-    double H[OR_MAXQ][OR_NMAX + 1][OR_TMAX]; /* H^(n)(xi_i), flattened */
+    real w[OR_MAXQ];
+    real r;
+    real xi[OR_MAXQ][3];
+    real H[OR_MAXQ][OR_NMAX + 1][OR_TMAX]; /* H^(n)(xi_i), flattened */
 } or_lattice;
 
 static or_lattice g_lat[2];
@@ -86,8 +94,8 @@ static int ipow(int b, int e)
 /*   a_0^(4)/rho = uuuu + (theta-1)(six uu delta) + (theta-1)^2 (three dd).    */
 /* Rank-n tensors are flat arrays of D^n entries, first index most significant.*/
 /* ------------------------------------------------------------------------- */
-static void hermite_like(int D, int nmax, const double *v, double kappa,
-                         double T[][OR_TMAX])
+static void hermite_like(int D, int nmax, const real *v, real kappa,
+                         real T[][OR_TMAX])
 {
     int pw[OR_NMAX + 2];
     pw[0] = 1;
@@ -96,7 +104,7 @@ static void hermite_like(int D, int nmax, const double *v, double kappa,
     for (int n = 0; n < nmax; ++n) {
         for (int a = 0; a < D; ++a) {
             for (int B = 0; B < pw[n]; ++B) {
-                double acc = v[a] * T[n][B];
+                real acc = v[a] * T[n][B];
                 for (int k = 0; k < n; ++k) {
                     int bk = (B / pw[n - 1 - k]) % D;
                     if (bk == a) {
@@ -111,9 +119,9 @@ static void hermite_like(int D, int nmax, const double *v, double kappa,
     }
 }
 
-static double contract(const double *A, const double *B, int len)
+static real contract(const real *A, const real *B, int len)
 {
-    double s = 0.0;
+    real s = 0.0;
     for (int k = 0; k < len; ++k) s += A[k] * B[k];
     return s;
 }
@@ -340,12 +348,12 @@ static int derive_lattice(int lattice, or_lattice *L)
     L->Q = sys.Q;
     L->degree = degree;
     L->max_eq_order = (degree - 1) / 2; /* Q_deg >= 2N (Sec. 2) */
-    L->r = (double)sqrtl(best_s);
+    L->r = (real)sqrtl(best_s);
     for (int q = 0; q < sys.Q; ++q) {
-        L->w[q] = (double)W[sys.shell_of[q]];
+        L->w[q] = (real)W[sys.shell_of[q]];
         for (int a = 0; a < 3; ++a) {
             L->c[q][a] = sys.c[q][a];
-            L->xi[q][a] = (double)(sqrtl(best_s) * (long double)sys.c[q][a]);
+            L->xi[q][a] = (real)(sqrtl(best_s) * (long double)sys.c[q][a]);
         }
         hermite_like(L->D, OR_NMAX, L->xi[q], -1.0, L->H[q]);
     }
@@ -366,16 +374,16 @@ static const or_lattice *get_lattice(int lattice)
 /* ------------------------------------------------------------------------- */
 
 /* Discrete equilibrium: f0_i = w_i sum_{n<=N} (1/n!) a_0^(n) : H^(n)(xi_i). */
-static void equilibrium(const or_lattice *L, int N, double rho, const double *u,
-                        double theta, double *feq)
+static void equilibrium(const or_lattice *L, int N, real rho, const real *u,
+                        real theta, real *feq)
 {
-    double A[OR_NMAX + 1][OR_TMAX];
+    real A[OR_NMAX + 1][OR_TMAX];
     int D = L->D;
     hermite_like(D, N, u, theta - 1.0, A);
     for (int i = 0; i < L->Q; ++i) {
-        double s = 0.0, fact = 1.0;
+        real s = 0.0, fact = 1.0;
         for (int n = 0; n <= N; ++n) {
-            if (n > 0) fact *= (double)n;
+            if (n > 0) fact *= (real)n;
             s += contract(A[n], L->H[i][n], ipow(D, n)) / fact;
         }
         feq[i] = L->w[i] * rho * s;
@@ -386,11 +394,11 @@ static void equilibrium(const or_lattice *L, int N, double rho, const double *u,
  * with a^(0)=rho, a^(1)=rho u, a^(2) = rho[uu + (theta-1) delta] - sigma.
  * Because H^(n) is symmetric, the normalised symmetric product contracts like
  * g_a a^(n-1)_B H^(n)_{aB}. */
-static void body_force(const or_lattice *L, int nf, int with_sigma, double rho,
-                       const double *u, double theta, const double *g,
-                       const double *sigma, double *F)
+static void body_force(const or_lattice *L, int nf, int with_sigma, real rho,
+                       const real *u, real theta, const real *g,
+                       const real *sigma, real *F)
 {
-    double A[OR_NMAX + 1][OR_TMAX];
+    real A[OR_NMAX + 1][OR_TMAX];
     int D = L->D;
     hermite_like(D, 2, u, theta - 1.0, A);
     for (int n = 0; n <= 2; ++n)
@@ -398,14 +406,14 @@ static void body_force(const or_lattice *L, int nf, int with_sigma, double rho,
     if (with_sigma)
         for (int k = 0; k < D * D; ++k) A[2][k] -= sigma[k];
     for (int i = 0; i < L->Q; ++i) {
-        double s = 0.0, fact = 1.0;
+        real s = 0.0, fact = 1.0;
         for (int n = 1; n <= nf; ++n) {
-            fact *= (double)n;
+            fact *= (real)n;
             int len = ipow(D, n - 1);
-            double dot = 0.0;
+            real dot = 0.0;
             for (int a = 0; a < D; ++a)
                 dot += g[a] * contract(A[n - 1], &L->H[i][n][a * len], len);
-            s += (double)n * dot / fact;
+            s += (real)n * dot / fact;
         }
         F[i] = L->w[i] * s;
     }
@@ -423,50 +431,50 @@ static int force_terms(int force_order, int *nf, int *with_sigma)
 }
 
 /* Moments of the stored populations of one cell and the mid-point values. */
-static void cell_moments(const or_lattice *L, const double *f, const double *g,
-                         double *rho_o, double *ub, double *theta_o)
+static void cell_moments(const or_lattice *L, const real *f, const real *g,
+                         real *rho_o, real *ub, real *theta_o)
 {
     int D = L->D;
-    double rho = 0.0, j[3] = {0, 0, 0}, E = 0.0;
+    real rho = 0.0, j[3] = {0, 0, 0}, E = 0.0;
     for (int i = 0; i < L->Q; ++i) {
         rho += f[i];
-        double x2 = 0.0;
+        real x2 = 0.0;
         for (int a = 0; a < D; ++a) {
             j[a] += f[i] * L->xi[i][a];
             x2 += L->xi[i][a] * L->xi[i][a];
         }
         E += f[i] * x2;
     }
-    double ut2 = 0.0, g2 = 0.0;
+    real ut2 = 0.0, g2 = 0.0;
     for (int a = 0; a < D; ++a) {
-        double ut = j[a] / rho;
+        real ut = j[a] / rho;
         ub[a] = ut + 0.5 * g[a];
         ut2 += ut * ut;
         g2 += g[a] * g[a];
     }
     *rho_o = rho;
-    *theta_o = (E / rho - ut2 + 0.25 * g2) / (double)D;
+    *theta_o = (E / rho - ut2 + 0.25 * g2) / (real)D;
 }
 
 /* sigma-bar of one cell, literal two-pass form, then trace removed. */
-static void cell_sigma(const or_lattice *L, const double *f, const double *feq,
-                       const double *ub, double tau_hat, double *sig)
+static void cell_sigma(const or_lattice *L, const real *f, const real *feq,
+                       const real *ub, real tau_hat, real *sig)
 {
     int D = L->D;
     for (int k = 0; k < 9; ++k) sig[k] = 0.0;
     for (int i = 0; i < L->Q; ++i) {
-        double dev = f[i] - feq[i];
+        real dev = f[i] - feq[i];
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b)
                 sig[a * D + b] += dev * (L->xi[i][a] - ub[a]) * (L->xi[i][b] - ub[b]);
     }
-    double pref = -(1.0 - 1.0 / (2.0 * tau_hat));
-    double tr = 0.0;
+    real pref = -(1.0 - 1.0 / (2.0 * tau_hat));
+    real tr = 0.0;
     for (int a = 0; a < D; ++a) tr += pref * sig[a * D + a];
     for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b) {
             sig[a * D + b] *= pref;
-            if (a == b) sig[a * D + b] -= tr / (double)D;
+            if (a == b) sig[a * D + b] -= tr / (real)D;
         }
 }
 
@@ -479,14 +487,14 @@ static int eq_order_of(const or_lattice *L, int eq_order)
 
 /* One collision: pre-collision f (stored variable) -> post-collision fs. */
 static void collide_cell(const or_lattice *L, int N, int nf, int with_sigma,
-                         double tau_hat, const double *f, const double *g, double *fs)
+                         real tau_hat, const real *f, const real *g, real *fs)
 {
-    double rho, ub[3] = {0, 0, 0}, theta, feq[OR_MAXQ], F[OR_MAXQ], sig[9];
+    real rho, ub[3] = {0, 0, 0}, theta, feq[OR_MAXQ], F[OR_MAXQ], sig[9];
     cell_moments(L, f, g, &rho, ub, &theta);
     equilibrium(L, N, rho, ub, theta, feq);
     if (with_sigma) cell_sigma(L, f, feq, ub, tau_hat, sig);
     body_force(L, nf, with_sigma, rho, ub, theta, g, sig, F);
-    double cf = 1.0 - 1.0 / (2.0 * tau_hat);
+    real cf = 1.0 - 1.0 / (2.0 * tau_hat);
     for (int i = 0; i < L->Q; ++i) fs[i] = f[i] - (f[i] - feq[i]) / tau_hat + cf * F[i];
 }
 
@@ -494,7 +502,7 @@ static void collide_cell(const or_lattice *L, int N, int nf, int with_sigma,
 /* Exported API (used through ctypes by the test suite)                       */
 /* ------------------------------------------------------------------------- */
 
-int oracle_lattice(int lattice, int *c, double *w, double *r, int *degree)
+int oracle_lattice(int lattice, int *c, real *w, real *r, int *degree)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L) return -1;
@@ -509,7 +517,7 @@ int oracle_lattice(int lattice, int *c, double *w, double *r, int *degree)
 }
 
 /* H^(n)(xi_i) for every velocity: out[i * D^n + k]. */
-int oracle_hermite(int lattice, int n, double *out)
+int oracle_hermite(int lattice, int n, real *out)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || n < 0 || n > OR_NMAX) return -1;
@@ -520,18 +528,18 @@ int oracle_hermite(int lattice, int n, double *out)
 }
 
 /* a_0^(n) of the Maxwellian with (rho, u, theta) in D dimensions. */
-int oracle_maxwell_coeff(int D, int n, double rho, const double *u, double theta, double *out)
+int oracle_maxwell_coeff(int D, int n, real rho, const real *u, real theta, real *out)
 {
     if (D < 1 || D > 3 || n < 0 || n > OR_NMAX) return -1;
-    double A[OR_NMAX + 1][OR_TMAX];
+    real A[OR_NMAX + 1][OR_TMAX];
     hermite_like(D, n, u, theta - 1.0, A);
     int len = ipow(D, n);
     for (int k = 0; k < len; ++k) out[k] = rho * A[n][k];
     return len;
 }
 
-int oracle_equilibrium(int lattice, int eq_order, double rho, const double *u,
-                       double theta, double *feq)
+int oracle_equilibrium(int lattice, int eq_order, real rho, const real *u,
+                       real theta, real *feq)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L) return -1;
@@ -542,14 +550,14 @@ int oracle_equilibrium(int lattice, int eq_order, double rho, const double *u,
 }
 
 /* sigma: D*D row-major (ignored unless force_order == 4). */
-int oracle_force(int lattice, int force_order, double rho, const double *u,
-                 double theta, const double *g, const double *sigma, double *F)
+int oracle_force(int lattice, int force_order, real rho, const real *u,
+                 real theta, const real *g, const real *sigma, real *F)
 {
     const or_lattice *L = get_lattice(lattice);
     int nf, ws;
     if (!L) return -1;
     if (force_terms(force_order, &nf, &ws) != 0) return -2;
-    double sig[9] = {0};
+    real sig[9] = {0};
     if (ws && sigma)
         for (int k = 0; k < L->D * L->D; ++k) sig[k] = sigma[k];
     body_force(L, nf, ws, rho, u, theta, g, sig, F);
@@ -577,8 +585,8 @@ static int check_grid(const or_lattice *L, int64_t nx, int64_t ny, int64_t nz)
 /* Fields are SoA: rho[N], u[a*N + cell], theta[N], g[a*N + cell];
  * populations are AoS: f[cell*Q + i]; cell = (z*ny + y)*nx + x. */
 int oracle_init(int lattice, int64_t nx, int64_t ny, int64_t nz, int eq_order, int force_order,
-                const double *rho, const double *u, const double *theta, const double *g,
-                double *f, int nthreads)
+                const real *rho, const real *u, const real *theta, const real *g,
+                real *f, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (check_grid(L, nx, ny, nz)) return -1;
@@ -589,8 +597,8 @@ int oracle_init(int lattice, int64_t nx, int64_t ny, int64_t nz, int eq_order, i
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < ncell; ++x) {
-        double uu[3] = {0, 0, 0}, gg[3] = {0, 0, 0}, feq[OR_MAXQ], F[OR_MAXQ];
-        double sig[9] = {0};
+        real uu[3] = {0, 0, 0}, gg[3] = {0, 0, 0}, feq[OR_MAXQ], F[OR_MAXQ];
+        real sig[9] = {0};
         for (int a = 0; a < D; ++a) {
             uu[a] = u[a * ncell + x];
             gg[a] = g[a * ncell + x];
@@ -609,8 +617,8 @@ static int64_t wrap(int64_t v, int64_t n)
 }
 
 /* nsteps collide-then-push steps; f holds the result, tmp is scratch. */
-int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, double tau_hat, int eq_order,
-                int force_order, const double *g, double *f, double *tmp, int64_t nsteps,
+int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, real tau_hat, int eq_order,
+                int force_order, const real *g, real *f, real *tmp, int64_t nsteps,
                 int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
@@ -621,12 +629,12 @@ int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, double tau_hat,
     int64_t ncell = nx * ny * nz;
     int D = L->D, Q = L->Q;
     set_threads(nthreads);
-    double *src = f, *dst = tmp;
+    real *src = f, *dst = tmp;
     for (int64_t s = 0; s < nsteps; ++s) {
 #pragma omp parallel for schedule(static)
         for (int64_t cell = 0; cell < ncell; ++cell) {
             int64_t x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
-            double gg[3] = {0, 0, 0}, fs[OR_MAXQ];
+            real gg[3] = {0, 0, 0}, fs[OR_MAXQ];
             for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + cell];
             collide_cell(L, N, nf, ws, tau_hat, &src[cell * Q], gg, fs);
             for (int i = 0; i < Q; ++i) {
@@ -636,17 +644,17 @@ int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, double tau_hat,
                 dst[((zd * ny + yd) * nx + xd) * Q + i] = fs[i];
             }
         }
-        double *t = src;
+        real *t = src;
         src = dst;
         dst = t;
     }
-    if (src != f) memcpy(f, src, (size_t)ncell * (size_t)Q * sizeof(double));
+    if (src != f) memcpy(f, src, (size_t)ncell * (size_t)Q * sizeof(real));
     return 0;
 }
 
 /* Physical moments at the current time: rho, u-bar = u~ + g/2, theta-bar. */
-int oracle_moments(int lattice, int64_t ncell, const double *f, const double *g,
-                   double *rho, double *u, double *theta, int nthreads)
+int oracle_moments(int lattice, int64_t ncell, const real *f, const real *g,
+                   real *rho, real *u, real *theta, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
@@ -654,7 +662,7 @@ int oracle_moments(int lattice, int64_t ncell, const double *f, const double *g,
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < ncell; ++x) {
-        double gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t;
+        real gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t;
         for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + x];
         cell_moments(L, &f[x * Q], gg, &r, ub, &t);
         rho[x] = r;
@@ -665,8 +673,8 @@ int oracle_moments(int lattice, int64_t ncell, const double *f, const double *g,
 }
 
 /* Mid-point deviatoric stress of every cell: sigma[(a*D+b)*N + cell]. */
-int oracle_sigma(int lattice, int64_t ncell, double tau_hat, int eq_order, const double *f,
-                 const double *g, double *sigma, int nthreads)
+int oracle_sigma(int lattice, int64_t ncell, real tau_hat, int eq_order, const real *f,
+                 const real *g, real *sigma, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
@@ -676,7 +684,7 @@ int oracle_sigma(int lattice, int64_t ncell, double tau_hat, int eq_order, const
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < ncell; ++x) {
-        double gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t, feq[OR_MAXQ], sig[9];
+        real gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t, feq[OR_MAXQ], sig[9];
         for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + x];
         cell_moments(L, &f[x * Q], gg, &r, ub, &t);
         equilibrium(L, N, r, ub, t, feq);
@@ -688,29 +696,29 @@ int oracle_sigma(int lattice, int64_t ncell, double tau_hat, int eq_order, const
 
 /* Heat flux q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical
  * distribution f = f0bar + (1 - 1/(2 tau^)) (f~ - f0bar + Fbar/2). */
-int oracle_heat_flux(int lattice, int64_t ncell, double tau_hat, int eq_order, int force_order,
-                     const double *f, const double *g, double *q, int nthreads)
+int oracle_heat_flux(int lattice, int64_t ncell, real tau_hat, int eq_order, int force_order,
+                     const real *f, const real *g, real *q, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
     int N = eq_order_of(L, eq_order), nf, ws;
     if (N < 0 || force_terms(force_order, &nf, &ws)) return -2;
     int D = L->D, Q = L->Q;
-    double cf = 1.0 - 1.0 / (2.0 * tau_hat);
+    real cf = 1.0 - 1.0 / (2.0 * tau_hat);
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < ncell; ++x) {
-        double gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t, feq[OR_MAXQ], F[OR_MAXQ];
-        double sig[9] = {0}, qq[3] = {0, 0, 0};
-        const double *fx = &f[x * Q];
+        real gg[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, r, t, feq[OR_MAXQ], F[OR_MAXQ];
+        real sig[9] = {0}, qq[3] = {0, 0, 0};
+        const real *fx = &f[x * Q];
         for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + x];
         cell_moments(L, fx, gg, &r, ub, &t);
         equilibrium(L, N, r, ub, t, feq);
         if (ws) cell_sigma(L, fx, feq, ub, tau_hat, sig);
         body_force(L, nf, ws, r, ub, t, gg, sig, F);
         for (int i = 0; i < Q; ++i) {
-            double fp = feq[i] + cf * (fx[i] - feq[i] + 0.5 * F[i]);
-            double c2 = 0.0;
+            real fp = feq[i] + cf * (fx[i] - feq[i] + 0.5 * F[i]);
+            real c2 = 0.0;
             for (int a = 0; a < D; ++a) c2 += (L->xi[i][a] - ub[a]) * (L->xi[i][a] - ub[a]);
             for (int a = 0; a < D; ++a) qq[a] += fp * c2 * (L->xi[i][a] - ub[a]);
         }
@@ -721,15 +729,15 @@ int oracle_heat_flux(int lattice, int64_t ncell, double tau_hat, int eq_order, i
 
 /* Global sums of the stored populations, serial, fixed order:
  * out = [sum f, sum f xi_a (a < D), sum f |xi|^2]. */
-int oracle_totals(int lattice, int64_t ncell, const double *f, double *out)
+int oracle_totals(int lattice, int64_t ncell, const real *f, real *out)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
     int D = L->D, Q = L->Q;
-    double m = 0.0, p[3] = {0, 0, 0}, e = 0.0;
+    real m = 0.0, p[3] = {0, 0, 0}, e = 0.0;
     for (int64_t x = 0; x < ncell; ++x) {
         for (int i = 0; i < Q; ++i) {
-            double fi = f[x * Q + i], x2 = 0.0;
+            real fi = f[x * Q + i], x2 = 0.0;
             m += fi;
             for (int a = 0; a < D; ++a) {
                 p[a] += fi * L->xi[i][a];

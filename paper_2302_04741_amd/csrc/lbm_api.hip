@@ -1,0 +1,390 @@
+// C ABI of the gfx950 thermal LBM library (declared in include/lbm.h).
+//
+// Host-side validation, workspace layout, handle state and launches on the
+// handle's stream.  The library allocates no device memory: every buffer is a
+// slice of the caller's workspace.  Argument checks run before any HIP call,
+// so they also work on a machine without a GPU.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+struct lbm_sim {
+    lbm_params p;
+    int D, Q, eq;
+    int64_t N;
+    GridDims gd;
+    StepCoef co;
+    ForceDesc fd;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    void *pop[2];
+    int cur;
+    void *gtab;
+    size_t gtab_bytes;
+    double *partials;
+    double *totals_dev;
+    int64_t step;
+    int block;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+lbm_status ok()
+{
+    g_err.clear();
+    return LBM_OK;
+}
+
+lbm_status dev_fail(hipError_t e, const char *what)
+{
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int lattice_dim(int lat) { return lat == LBM_D2Q37 ? D2Q37_D : D3Q39_D; }
+int lattice_q(int lat) { return lat == LBM_D2Q37 ? D2Q37_Q : D3Q39_Q; }
+int lattice_maxeq(int lat) { return lat == LBM_D2Q37 ? Lattice<0>::MAXEQ : Lattice<1>::MAXEQ; }
+size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+size_t arith_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+struct Layout {
+    size_t pop, gtab, partials, totals;
+    size_t off_pop1, off_gtab, off_part, off_tot, total;
+};
+
+Layout layout_of(const lbm_params *p)
+{
+    Layout L{};
+    const int D = lattice_dim(p->lattice), Q = lattice_q(p->lattice);
+    const size_t N = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
+    L.pop = align_up(size_t(Q) * N * storage_bytes(p->storage));
+    int64_t ext = p->nx > p->ny ? p->nx : p->ny;
+    ext = ext > p->nz ? ext : p->nz;
+    size_t gcount = size_t(D) * size_t(ext);
+    if (p->flags & LBM_FLAG_FORCE_FIELD) {
+        const size_t gf = size_t(D) * N;
+        gcount = gcount > gf ? gcount : gf;
+    }
+    L.gtab = align_up(gcount * arith_bytes(p->storage));
+    L.partials = align_up(size_t(TOTALS_BLOCKS) * size_t(Q) * sizeof(double));
+    L.totals = align_up(8 * sizeof(double));
+    L.off_pop1 = L.pop;
+    L.off_gtab = 2 * L.pop;
+    L.off_part = L.off_gtab + L.gtab;
+    L.off_tot = L.off_part + L.partials;
+    L.total = L.off_tot + L.totals;
+    return L;
+}
+
+lbm_status check_params(const lbm_params *p)
+{
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(lbm_params))
+        return fail(LBM_EINVAL, "params.struct_size is %u, expected %zu", p->struct_size,
+                    sizeof(lbm_params));
+    if (p->lattice != LBM_D2Q37 && p->lattice != LBM_D3Q39)
+        return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
+    if (p->storage != LBM_F64 && p->storage != LBM_F32 && p->storage != LBM_F16DEV)
+        return fail(LBM_EINVAL, "unknown storage %d", p->storage);
+    if (p->storage == LBM_F16DEV)
+        return fail(LBM_EUNSUPPORTED, "LBM_F16DEV storage is not available in this build");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LBM_EINVAL, "grid extents must be >= 1 (got %lld x %lld x %lld)",
+                    (long long)p->nx, (long long)p->ny, (long long)p->nz);
+    if (p->lattice == LBM_D2Q37 && p->nz != 1)
+        return fail(LBM_EINVAL, "D2Q37 needs nz == 1 (got %lld)", (long long)p->nz);
+    if (p->nx > (int64_t(1) << 30) || p->ny > 65535 || p->nz > 65535)
+        return fail(LBM_EUNSUPPORTED, "grid extents limited to nx <= 2^30, ny, nz <= 65535");
+    const double cells = double(p->nx) * double(p->ny) * double(p->nz);
+    if (cells * lattice_q(p->lattice) * storage_bytes(p->storage) > 4.0e12)
+        return fail(LBM_EUNSUPPORTED, "grid too large");
+    if (!std::isfinite(p->tau_hat) || !(p->tau_hat > 0.5))
+        return fail(LBM_EINVAL, "tau_hat must be finite and > 0.5 (got %g)", p->tau_hat);
+    if (p->eq_order < 0 || p->eq_order == 1)
+        return fail(LBM_EINVAL, "eq_order must be 0 or >= 2 (got %d)", p->eq_order);
+    if (p->eq_order > lattice_maxeq(p->lattice))
+        return fail(LBM_EUNSUPPORTED, "eq_order %d exceeds what the velocity set supports (%d)",
+                    p->eq_order, lattice_maxeq(p->lattice));
+    if (p->force_order < LBM_FORCE_N0 || p->force_order > LBM_FORCE_N2)
+        return fail(LBM_EINVAL, "unknown force_order %d", p->force_order);
+    if (p->flags & ~LBM_FLAG_FORCE_FIELD) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+    if (!std::isfinite(p->rho0) || !(p->rho0 >= 0))
+        return fail(LBM_EINVAL, "rho0 must be finite and >= 0 (got %g)", p->rho0);
+    return LBM_OK;
+}
+
+LaunchCfg cfg(const lbm_sim *s) { return LaunchCfg{s->block, s->stream}; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params *p)
+{
+    if (check_params(p) != LBM_OK) return 0;
+    return layout_of(p).total;
+}
+
+lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_bytes,
+                      void *hip_stream, const double *rho, const double *u, const double *theta,
+                      lbm_sim **out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    lbm_status st = check_params(p);
+    if (st != LBM_OK) return st;
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN)
+        return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    const Layout L = layout_of(p);
+    if (workspace_bytes < L.total)
+        return fail(LBM_ENOSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    if (!rho || !u || !theta) return fail(LBM_EINVAL, "initial fields must not be NULL");
+
+    lbm_sim *s = new (std::nothrow) lbm_sim();
+    if (!s) return fail(LBM_EINVAL, "out of host memory");
+    s->p = *p;
+    s->D = lattice_dim(p->lattice);
+    s->Q = lattice_q(p->lattice);
+    s->eq = p->eq_order ? p->eq_order : lattice_maxeq(p->lattice);
+    s->N = p->nx * p->ny * p->nz;
+    s->gd = GridDims{int32_t(p->nx), int32_t(p->ny), int32_t(p->nz), 0, s->N};
+    s->co = StepCoef{1.0 / p->tau_hat, 1.0 - 0.5 / p->tau_hat, p->rho0};
+    s->fd = ForceDesc{};
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->ws = static_cast<char *>(workspace);
+    s->ws_bytes = workspace_bytes;
+    s->pop[0] = s->ws;
+    s->pop[1] = s->ws + L.off_pop1;
+    s->cur = 0;
+    s->gtab = s->ws + L.off_gtab;
+    s->gtab_bytes = L.gtab;
+    s->fd.tab = s->gtab;
+    s->partials = reinterpret_cast<double *>(s->ws + L.off_part);
+    s->totals_dev = reinterpret_cast<double *>(s->ws + L.off_tot);
+    s->step = 0;
+    s->block = 0;
+    hipError_t e = launch_init(p->lattice, p->storage, s->eq, p->force_order, rho, u, theta,
+                               s->pop[0], s->gd, s->fd, s->co, cfg(s));
+    if (e != hipSuccess) {
+        delete s;
+        return dev_fail(e, "init kernel launch");
+    }
+    *out = s;
+    return ok();
+}
+
+lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis, int64_t len)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!g) return fail(LBM_EINVAL, "g is NULL");
+    ForceDesc nf = s->fd;
+    nf.tab = s->gtab;
+    int64_t count = 0;
+    if (kind == LBM_G_UNIFORM) {
+        for (int a = 0; a < s->D; ++a)
+            if (!std::isfinite(g[a])) return fail(LBM_EINVAL, "g[%d] is not finite", a);
+        nf.kind = 0;
+        for (int a = 0; a < 3; ++a) nf.g[a] = a < s->D ? g[a] : 0.0;
+        nf.axis = 0;
+        nf.len = 0;
+    } else if (kind == LBM_G_AXIS_PROFILE) {
+        if (axis < 0 || axis >= s->D) return fail(LBM_EINVAL, "axis %d out of range", axis);
+        const int64_t ext = axis == 0 ? s->p.nx : (axis == 1 ? s->p.ny : s->p.nz);
+        if (len != ext)
+            return fail(LBM_EINVAL, "profile length %lld must equal the extent %lld along axis %d",
+                        (long long)len, (long long)ext, axis);
+        nf.kind = 1;
+        nf.axis = axis;
+        nf.len = len;
+        count = int64_t(s->D) * len;
+    } else if (kind == LBM_G_FIELD) {
+        if (!(s->p.flags & LBM_FLAG_FORCE_FIELD))
+            return fail(LBM_EINVAL, "LBM_G_FIELD needs LBM_FLAG_FORCE_FIELD at creation");
+        nf.kind = 2;
+        nf.axis = 0;
+        nf.len = 0;
+        count = int64_t(s->D) * s->N;
+    } else {
+        return fail(LBM_EINVAL, "unknown force kind %d", kind);
+    }
+    if (size_t(count) * arith_bytes(s->p.storage) > s->gtab_bytes)
+        return fail(LBM_ENOSPACE, "force table does not fit the workspace");
+
+    hipError_t e;
+    void *scratch = s->pop[s->cur ^ 1];
+    double *mrho = static_cast<double *>(scratch);
+    double *mu = mrho + s->N;
+    double *mth = mu + int64_t(s->D) * s->N;
+    if (s->step == 0) {
+        // Rebuild f~ = f0 - F/2 for the new force from the current moments,
+        // which were produced with the old one.  The idle population buffer
+        // holds the FP64 moments in between ((2 + D) doubles per cell fit in
+        // Q stored values for every storage type).
+        e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], mrho, mu, mth, s->gd, s->fd,
+                           s->co, cfg(s));
+        if (e != hipSuccess) return dev_fail(e, "moments kernel launch");
+    }
+    if (count > 0) {
+        e = launch_convert(s->p.storage, g, s->gtab, count, s->stream);
+        if (e != hipSuccess) return dev_fail(e, "force table conversion");
+    }
+    s->fd = nf;
+    if (s->step == 0) {
+        e = launch_init(s->p.lattice, s->p.storage, s->eq, s->p.force_order, mrho, mu, mth,
+                        s->pop[s->cur], s->gd, s->fd, s->co, cfg(s));
+        if (e != hipSuccess) return dev_fail(e, "init kernel launch");
+    }
+    return ok();
+}
+
+lbm_status lbm_step(lbm_sim *s, int64_t nsteps)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
+                                   s->pop[s->cur], s->pop[s->cur ^ 1], s->gd, s->fd, s->co, cfg(s));
+        if (e != hipSuccess) return dev_fail(e, "step kernel launch");
+        s->cur ^= 1;
+        s->step++;
+    }
+    return ok();
+}
+
+lbm_status lbm_moments(lbm_sim *s, double *rho, double *u, double *theta)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!rho && !u && !theta) return ok();
+    hipError_t e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], rho, u, theta,
+                                  s->gd, s->fd, s->co, cfg(s));
+    if (e != hipSuccess) return dev_fail(e, "moments kernel launch");
+    return ok();
+}
+
+void lbm_destroy(lbm_sim *s) { delete s; }
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_totals(lbm_sim *s, double *out)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    hipError_t e = launch_totals(s->p.lattice, s->p.storage, s->pop[s->cur], s->partials,
+                                 s->totals_dev, s->gd, s->co, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "totals kernel launch");
+    e = hipMemcpyAsync(out, s->totals_dev, sizeof(double) * size_t(s->D + 2),
+                       hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "totals copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return dev_fail(e, "stream synchronize");
+    for (int k = 0; k < s->D + 2; ++k)
+        if (!std::isfinite(out[k])) return fail(LBM_ENONFINITE, "total %d is not finite", k);
+    return ok();
+}
+
+lbm_status lbm_heat_flux(lbm_sim *s, double *q)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!q) return fail(LBM_EINVAL, "q is NULL");
+    hipError_t e = launch_heat_flux(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
+                                    s->pop[s->cur], q, s->gd, s->fd, s->co, cfg(s));
+    if (e != hipSuccess) return dev_fail(e, "heat-flux kernel launch");
+    return ok();
+}
+
+size_t lbm_population_bytes(const lbm_sim *s)
+{
+    if (!s) return 0;
+    return size_t(s->Q) * size_t(s->N) * storage_bytes(s->p.storage);
+}
+
+lbm_status lbm_get_populations(lbm_sim *s, void *dst)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+    hipError_t e = hipMemcpyAsync(dst, s->pop[s->cur], lbm_population_bytes(s),
+                                  hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "population copy");
+    return ok();
+}
+
+lbm_status lbm_set_populations(lbm_sim *s, const void *src)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!src) return fail(LBM_EINVAL, "src is NULL");
+    hipError_t e = hipMemcpyAsync(s->pop[s->cur], src, lbm_population_bytes(s),
+                                  hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "population copy");
+    return ok();
+}
+
+int64_t lbm_step_count(const lbm_sim *s) { return s ? s->step : -1; }
+
+lbm_status lbm_set_step_count(lbm_sim *s, int64_t n)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "step count must be >= 0");
+    s->step = n;
+    return ok();
+}
+
+lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return ok();
+}
+
+lbm_status lbm_set_block(lbm_sim *s, int32_t threads)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
+        threads != 1024)
+        return fail(LBM_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024 (got %d)", threads);
+    s->block = threads;
+    return ok();
+}
+
+int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
+{
+    if (lattice != LBM_D2Q37 && lattice != LBM_D3Q39)
+        return int32_t(fail(LBM_EINVAL, "unknown lattice %d", lattice));
+    const int Q = lattice_q(lattice);
+    for (int i = 0; i < Q; ++i) {
+        for (int a = 0; a < 3; ++a)
+            if (c) c[3 * i + a] = lattice == LBM_D2Q37 ? d2q37_C[i][a] : d3q39_C[i][a];
+        if (w) w[i] = lattice == LBM_D2Q37 ? d2q37_WSHELL[d2q37_SHELL[i]] : d3q39_WSHELL[d3q39_SHELL[i]];
+    }
+    if (r) *r = lattice == LBM_D2Q37 ? d2q37_R : d3q39_R;
+    ok();
+    return Q;
+}
+
+const char *lbm_version(void) { return "lbm-gfx950 0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Generic launchers: switch on lattice and storage to the per-lattice pieces.
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+template <class T>
+__global__ void __launch_bounds__(256) convert_kernel(const double *__restrict__ src,
+                                                      T *__restrict__ dst, int64_t n)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = T(src[k]);
+}
+}  // namespace
+
+hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void *B,
+                       const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                       const LaunchCfg &lc)
+{
+    if (lat == 0 && storage == 0) return launch_step_ls<0, double>(eq, fo, A, B, gd, fd, co, lc);
+    if (lat == 0 && storage == 1) return launch_step_ls<0, float>(eq, fo, A, B, gd, fd, co, lc);
+    if (lat == 1 && storage == 0) return launch_step_ls<1, double>(eq, fo, A, B, gd, fd, co, lc);
+    if (lat == 1 && storage == 1) return launch_step_ls<1, float>(eq, fo, A, B, gd, fd, co, lc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(int lat, int storage, int eq, int fo, const double *rho, const double *u,
+                       const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
+                       const StepCoef &co, const LaunchCfg &lc)
+{
+    if (lat == 0) return launch_init_l<0>(storage, eq, fo, rho, u, theta, A, gd, fd, co, lc);
+    if (lat == 1) return launch_init_l<1>(storage, eq, fo, rho, u, theta, A, gd, fd, co, lc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments(int lat, int storage, const void *A, double *rho, double *u,
+                          double *theta, const GridDims &gd, const ForceDesc &fd,
+                          const StepCoef &co, const LaunchCfg &lc)
+{
+    if (lat == 0) return launch_moments_l<0>(storage, A, rho, u, theta, gd, fd, co, lc);
+    if (lat == 1) return launch_moments_l<1>(storage, A, rho, u, theta, gd, fd, co, lc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_heat_flux(int lat, int storage, int eq, int fo, const void *A, double *q,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc)
+{
+    if (lat == 0) return launch_heat_flux_l<0>(storage, eq, fo, A, q, gd, fd, co, lc);
+    if (lat == 1) return launch_heat_flux_l<1>(storage, eq, fo, A, q, gd, fd, co, lc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_totals(int lat, int storage, const void *A, double *partials, double *out_dev,
+                         const GridDims &gd, const StepCoef &co, hipStream_t stream)
+{
+    if (lat == 0) return launch_totals_l<0>(storage, A, partials, out_dev, gd, co, stream);
+    if (lat == 1) return launch_totals_l<1>(storage, A, partials, out_dev, gd, co, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_convert(int storage, const double *src, void *dst, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = unsigned((n + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((convert_kernel<double>), dim3(nb), dim3(256), 0, stream, src,
+                           static_cast<double *>(dst), n);
+    else
+        hipLaunchKernelGGL((convert_kernel<float>), dim3(nb), dim3(256), 0, stream, src,
+                           static_cast<float *>(dst), n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,457 @@
+// Internal declarations of the gfx950 thermal LBM library: lattice traits, the
+// per-cell arithmetic shared by the kernels, kernel argument blocks and the
+// launchers called by the C ABI layer.
+//
+// Method (Li & Shan, arXiv:2302.04741, Sec. 2):
+//   stored variable f~ (auxiliary variable of the trapezoidal time integration);
+//   mid-point moments rho, u = u~ + g/2, theta = (E/rho - |u~|^2 + |g|^2/4)/D;
+//   equilibrium = Hermite expansion of the Maxwellian to order N, eq. (fN);
+//   force       = Hermite expansion eq. (F) to the third moment, eq. (fi);
+//   sigma-bar   = -(1 - 1/(2 tau^)) sum_i (f~_i - f0_i)(xi_i - u)(xi_i - u), traceless;
+//   step        = eq. (lbm): f~(x + xi_i, t+1) = f~ - (f~ - f0)/tau^ + (1 - 1/(2 tau^)) F.
+// Everything here is written as closed-form polynomials in xi.u, xi.g and
+// xi.sigma.xi with per-shell constants, and shares the even/odd parts of each
+// +c/-c velocity pair.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lattice_tables.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// compile-time loops
+// ---------------------------------------------------------------------------
+template <int I, int N, typename F>
+__host__ __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(static_cast<F &&>(f));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lattice traits (velocity order: rest, then +c/-c pairs shell by shell)
+// ---------------------------------------------------------------------------
+template <int LAT> struct Lattice;
+
+template <> struct Lattice<0> {
+    static constexpr int D = D2Q37_D, Q = D2Q37_Q, NS = D2Q37_NSHELL, MAXEQ = 4;
+    // r^2 as R*R (not the separately rounded r^2) keeps xi^2 consistent with xi = R c
+    static constexpr double R = d2q37_R, R2 = d2q37_R * d2q37_R;
+    static constexpr int c(int i, int a) { return d2q37_C[i][a]; }
+    static constexpr int shell(int i) { return d2q37_SHELL[i]; }
+    static constexpr double wshell(int s) { return d2q37_WSHELL[s]; }
+};
+
+template <> struct Lattice<1> {
+    static constexpr int D = D3Q39_D, Q = D3Q39_Q, NS = D3Q39_NSHELL, MAXEQ = 3;
+    static constexpr double R = d3q39_R, R2 = d3q39_R * d3q39_R;
+    static constexpr int c(int i, int a) { return d3q39_C[i][a]; }
+    static constexpr int shell(int i) { return d3q39_SHELL[i]; }
+    static constexpr double wshell(int s) { return d3q39_WSHELL[s]; }
+};
+
+template <class L> constexpr int c2(int i)
+{
+    return L::c(i, 0) * L::c(i, 0) + L::c(i, 1) * L::c(i, 1) + L::c(i, 2) * L::c(i, 2);
+}
+
+// ---------------------------------------------------------------------------
+// storage conversion
+// ---------------------------------------------------------------------------
+// Every storage type holds the deviations h_i = f_i - w_i rho0.  LBM_F16DEV
+// stores h_i * 2^k_i as binary16, with k_i = round(-log2 w_i): the exact
+// power-of-two scale brings deviations of the size of w_i to about one, far
+// from the subnormal range of binary16.
+template <class L> struct DevScale {
+    static constexpr int k(int i)
+    {
+        // k_i = round(-log2(w_i)): an exact power of two, chosen so that a
+        // deviation comparable to w_i is stored near 1.
+        double w = L::wshell(L::shell(i));
+        int e = 0;
+        while (w < 0.70710678118654752) {
+            w *= 2.0;
+            ++e;
+        }
+        return e;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// argument blocks
+// ---------------------------------------------------------------------------
+struct GridDims {
+    int32_t nx, ny, nz;
+    int32_t pad;
+    int64_t N;  // nx*ny*nz
+};
+
+struct ForceDesc {
+    int32_t kind;  // 0 uniform, 1 axis profile, 2 field
+    int32_t axis;  // profile axis
+    int64_t len;   // profile length
+    double g[3];   // uniform value
+    const void *tab;  // profile (D*len) or field (D*N), arithmetic precision
+};
+
+struct StepCoef {
+    double om;   // 1/tau^
+    double cf;   // 1 - 1/(2 tau^)
+    double rho0; // reference density of F16 deviations
+};
+
+// Periodic wrap of v in [-3, n + 3) into [0, n), valid for any n >= 1.
+__device__ __forceinline__ int wrap3(int v, int n)
+{
+    if (n >= 4) {
+        v += (v < 0) ? n : 0;
+        v -= (v >= n) ? n : 0;
+        return v;
+    }
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// body force at a cell
+// ---------------------------------------------------------------------------
+// TT: element type of the force table (the arithmetic precision of the
+// storage), TO: output type.
+template <class TT, class TO, int D>
+__device__ __forceinline__ void load_force(const ForceDesc &fd, const GridDims &gd, int x, int y,
+                                           int z, int64_t cell, TO g[3])
+{
+    g[0] = g[1] = g[2] = TO(0);
+    if (fd.kind == 0) {
+        for (int a = 0; a < D; ++a) g[a] = TO(TT(fd.g[a]));
+    } else if (fd.kind == 1) {
+        const TT *tab = static_cast<const TT *>(fd.tab);
+        const int k = fd.axis == 0 ? x : (fd.axis == 1 ? y : z);
+        for (int a = 0; a < D; ++a) g[a] = TO(tab[a * fd.len + k]);
+    } else {
+        const TT *tab = static_cast<const TT *>(fd.tab);
+        for (int a = 0; a < D; ++a) g[a] = TO(tab[a * gd.N + cell]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-cell state after the moment pass
+// ---------------------------------------------------------------------------
+template <class T> struct CellState {
+    T rho;
+    T drho;      // rho - rho0
+    T ub[3];     // mid-point velocity u~ + g/2
+    T th;        // mid-point temperature
+    T g[3];
+    T sig[3][3]; // mid-point deviatoric stress (traceless), zero unless needed
+};
+
+// Raw sums of one cell over the stored deviations h_i = f_i - w_i rho0:
+// drho = sum h, j = sum h c (integer c), P = sum h c c.  Because the weights
+// satisfy sum w = 1, sum w c = 0 and sum w c c = delta / r^2, the moments of f
+// follow as rho = rho0 + drho, sum f xi = r j, sum f xi xi = rho0 delta + r^2 P.
+template <class T> struct RawSums {
+    T drho, j[3], P[3][3];
+};
+
+template <class L, class T>
+__device__ __forceinline__ RawSums<T> raw_sums(const T (&h)[L::Q])
+{
+    RawSums<T> s;
+    s.drho = h[0];
+    for (int a = 0; a < 3; ++a) {
+        s.j[a] = T(0);
+        for (int b = 0; b < 3; ++b) s.P[a][b] = T(0);
+    }
+    static_for<0, (L::Q - 1) / 2>([&](auto K) {
+        constexpr int ip = 1 + 2 * decltype(K)::value;
+        constexpr int im = ip + 1;
+        const T sp = h[ip] + h[im];
+        const T dm = h[ip] - h[im];
+        s.drho += sp;
+        static_for<0, L::D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int ca = L::c(ip, a);
+            if constexpr (ca == 1) s.j[a] += dm;
+            else if constexpr (ca == -1) s.j[a] -= dm;
+            else if constexpr (ca != 0) s.j[a] += T(ca) * dm;
+            static_for<a, L::D>([&](auto B) {
+                constexpr int b = decltype(B)::value;
+                constexpr int cab = ca * L::c(ip, b);
+                if constexpr (cab == 1) s.P[a][b] += sp;
+                else if constexpr (cab == -1) s.P[a][b] -= sp;
+                else if constexpr (cab != 0) s.P[a][b] += T(cab) * sp;
+            });
+        });
+    });
+    return s;
+}
+
+// Mid-point moments and (if WITH_SIGMA) sigma-bar from the raw sums.
+//   rho = rho0 + drho, u = r j / rho + g/2,
+//   theta = (E/rho - |u~|^2 + |g|^2/4)/D with E = rho0 D + r^2 tr P;
+//   sigma-bar = -cf [sum f xi xi - rho(u u + theta delta) + rho (u g + g u)/2]
+//   with its trace removed.  The isotropic parts (rho0 delta and
+//   rho theta delta) drop out of the traceless projection exactly, so they are
+//   left out: sigma-bar = dev(-cf [r^2 P - rho u u + rho (u g + g u)/2]).
+template <class L, class T, bool WITH_SIGMA>
+__device__ __forceinline__ void finish_moments(const RawSums<T> &s, const T g[3], T cf, T rho0,
+                                               CellState<T> &cs)
+{
+    constexpr int D = L::D;
+    const T r = T(L::R), r2 = T(L::R2);
+    const T rho = rho0 + s.drho;
+    const T inv = T(1) / rho;
+    T ut2 = T(0), g2 = T(0), tr = T(0);
+    cs.rho = rho;
+    cs.drho = s.drho;
+    for (int a = 0; a < 3; ++a) {
+        cs.g[a] = g[a];
+        cs.ub[a] = T(0);
+    }
+    for (int a = 0; a < D; ++a) {
+        const T ut = r * s.j[a] * inv;
+        cs.ub[a] = ut + T(0.5) * g[a];
+        ut2 += ut * ut;
+        g2 += g[a] * g[a];
+        tr += s.P[a][a];
+    }
+    const T E = rho0 * T(D) + r2 * tr;
+    cs.th = (E * inv - ut2 + T(0.25) * g2) * T(1.0 / D);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) cs.sig[a][b] = T(0);
+    if constexpr (WITH_SIGMA) {
+        T str = T(0);
+        for (int a = 0; a < D; ++a) {
+            for (int b = a; b < D; ++b) {
+                T v = r2 * s.P[a][b] - rho * cs.ub[a] * cs.ub[b]
+                      + T(0.5) * rho * (cs.ub[a] * g[b] + g[a] * cs.ub[b]);
+                v *= -cf;
+                cs.sig[a][b] = v;
+                cs.sig[b][a] = v;
+            }
+            str += cs.sig[a][a];
+        }
+        for (int a = 0; a < D; ++a) cs.sig[a][a] -= str * T(1.0 / D);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// alpha * f0 + beta * F for every velocity, in even/odd pair form.
+//
+// For velocity xi_i in shell s (xi^2 = X2) with xu = xi.u, xg = xi.g,
+// u2 = |u|^2, t = theta - 1, gu = g.u:
+//   f0 = w rho [ e(xu^2) + o(xu) ],  e even, o odd in xi:
+//     e = 1 + (xu^2 - u2 + t(X2 - D))/2
+//         + [xu^4 - 6 xu^2 u2 + 3 u2^2 + 6t(xu^2(X2 - D - 4) + u2(D + 2 - X2))
+//            + 3t^2(X2^2 - 2(D+2) X2 + D(D+2))]/24            (N = 4)
+//     o = xu [1 + (xu^2 - 3 u2 + 3t(X2 - D - 2))/6]           (N >= 3; xu for N = 2)
+//   F (eq. (fi)) even part  w rho (xg xu - gu)                (order >= 2)
+//     odd part  w rho xg                                       (order 1, 2)
+//               w rho [xg (1 + (xu^2 - u2 + t(X2 - D - 2))/2) - gu xu]   (order >= 3)
+//               - (w/2) [xg (xi.sigma.xi) - 2 xi.sigma.g]     (order 4)
+// With NO_BASE the even part omits alpha * w * rho (the leading term of f0),
+// so that callers can add it as an exactly rounded increment.
+// The callback receives (i_plus, i_minus, even, odd) for each pair and
+// (0, -1, even, 0) for the rest velocity; the indices are passed as
+// std::integral_constant so that callers index register arrays statically.
+// ---------------------------------------------------------------------------
+template <class L, class T, int EQ, int FO, bool NO_BASE = false, class CB>
+__device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T beta, CB &&cb)
+{
+    constexpr int D = L::D;
+    const T r = T(L::R), r2 = T(L::R2);
+    T ur[3], gr[3], hr[3], sr[3][3];
+    T u2 = T(0), gu = T(0);
+    for (int a = 0; a < 3; ++a) {
+        ur[a] = r * cs.ub[a];
+        gr[a] = r * cs.g[a];
+        hr[a] = T(0);
+    }
+    for (int a = 0; a < D; ++a) {
+        u2 += cs.ub[a] * cs.ub[a];
+        gu += cs.g[a] * cs.ub[a];
+    }
+    if constexpr (FO == 4) {
+        for (int a = 0; a < D; ++a) {
+            T h = T(0);
+            for (int b = 0; b < D; ++b) {
+                h += cs.sig[a][b] * cs.g[b];
+                sr[a][b] = r2 * cs.sig[a][b];
+            }
+            hr[a] = r * h;
+        }
+    }
+    const T t = cs.th - T(1);
+    const T rho = cs.rho;
+
+    // per-shell constants, recomputed at the first pair of each shell
+    T K0 = T(0), Ka = T(0), Kq = T(0), K6 = T(0), Kb = T(0), Kb2 = T(0), Kw = T(0), K24 = T(0);
+    T Kbf = T(0);
+    auto shell_consts = [&](auto S) {
+        constexpr int s = decltype(S)::value;
+        // any velocity of the shell gives X2
+        constexpr int iref = [] {
+            int i = 0;
+            while (L::shell(i) != s) ++i;
+            return i;
+        }();
+        constexpr double X2d = L::R2 * c2<L>(iref);
+        const T X2 = T(X2d);
+        const T wr = T(L::wshell(s)) * rho;
+        const T A = alpha * wr;      // multiplies the equilibrium bracket
+        const T Bf = beta * wr;      // multiplies the force bracket
+        // e0 - 1, computed without the leading 1
+        const T e0m1 = T(0.5) * (t * (X2 - T(D)) - u2);
+        T e0t = NO_BASE ? e0m1 : T(1) + e0m1, e1 = T(0.5);
+        if constexpr (EQ == 4) {
+            e0t += (T(3) * u2 * u2 + T(6) * t * u2 * (T(D + 2) - X2)
+                    + T(3) * t * t * (X2 * X2 - T(2 * (D + 2)) * X2 + T(D * (D + 2))))
+                   * T(1.0 / 24.0);
+            e1 += (t * (X2 - T(D + 4)) - u2) * T(0.25);
+            K24 = A * T(1.0 / 24.0);
+        }
+        const T o0 = T(1) - T(0.5) * u2 + T(0.5) * t * (X2 - T(D + 2));
+        K0 = A * e0t;                   // even constant
+        if constexpr (FO >= 2) K0 -= Bf * gu;
+        Ka = A * e1;                    // even, times xu^2
+        if constexpr (EQ >= 3) {
+            Kq = A * o0;                // odd, times xu
+            K6 = A * T(1.0 / 6.0);      // odd, times xu^3
+        } else {
+            Kq = A;
+            K6 = T(0);
+        }
+        if constexpr (FO >= 3) {
+            Kq -= Bf * gu;
+            Kb = Bf * o0;               // odd, times xg
+            Kb2 = Bf * T(0.5);          // odd, times xg xu^2
+        } else {
+            Kb = Bf;
+            Kb2 = T(0);
+        }
+        Kbf = Bf;                       // even, times xg xu
+        Kw = beta * T(0.5 * L::wshell(s));  // (beta w / 2) for the sigma terms
+    };
+
+    // rest velocity
+    shell_consts(std::integral_constant<int, L::shell(0)>{});
+    cb(std::integral_constant<int, 0>{}, std::integral_constant<int, -1>{}, K0, T(0));
+
+    static_for<0, (L::Q - 1) / 2>([&](auto K) {
+        constexpr int ip = 1 + 2 * decltype(K)::value;
+        constexpr int im = ip + 1;
+        constexpr int s = L::shell(ip);
+        if constexpr (L::shell(ip - 1) != s) shell_consts(std::integral_constant<int, s>{});
+        constexpr int cx = L::c(ip, 0), cy = L::c(ip, 1), cz = L::c(ip, 2);
+        // xi.u and xi.g with compile-time integer components
+        auto dot = [&](const T v[3]) {
+            T acc = T(0);
+            bool first = true;
+            static_for<0, 3>([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                constexpr int ca = (a == 0 ? cx : (a == 1 ? cy : cz));
+                if constexpr (ca != 0) {
+                    if (first) {
+                        acc = (ca == 1) ? v[a] : ((ca == -1) ? -v[a] : T(ca) * v[a]);
+                        first = false;
+                    } else {
+                        if constexpr (ca == 1) acc += v[a];
+                        else if constexpr (ca == -1) acc -= v[a];
+                        else acc += T(ca) * v[a];
+                    }
+                }
+            });
+            return acc;
+        };
+        const T xu = dot(ur);
+        const T xu2 = xu * xu;
+        T ev = K0 + Ka * xu2;
+        if constexpr (EQ == 4) ev += K24 * xu2 * xu2;
+        T od = xu * (Kq + K6 * xu2);
+        if constexpr (FO >= 1) {
+            const T xg = dot(gr);
+            if constexpr (FO >= 2) ev += Kbf * (xg * xu);
+            T gterm = Kb + Kb2 * xu2;
+            if constexpr (FO == 4) {
+                // xi.sigma.xi = r^2 c.sigma.c and xi.sigma.g = r c.(sigma g)
+                T S = T(0);
+                static_for<0, 3>([&](auto A) {
+                    constexpr int a = decltype(A)::value;
+                    constexpr int ca = (a == 0 ? cx : (a == 1 ? cy : cz));
+                    static_for<a, 3>([&](auto B) {
+                        constexpr int b = decltype(B)::value;
+                        constexpr int cb_ = (b == 0 ? cx : (b == 1 ? cy : cz));
+                        constexpr int m = (a == b) ? ca * cb_ : 2 * ca * cb_;
+                        if constexpr (m != 0) S += T(m) * sr[a][b];
+                    });
+                });
+                const T hxi = dot(hr);
+                gterm -= Kw * S;
+                od += T(2) * Kw * hxi;
+            }
+            od += xg * gterm;
+        }
+        cb(std::integral_constant<int, ip>{}, std::integral_constant<int, im>{}, ev, od);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+struct LaunchCfg {
+    int block;  // threads along x per block
+    hipStream_t stream;
+};
+
+// Generic entry points (lbm_dispatch.hip), switching on lattice and storage.
+hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void *B,
+                       const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                       const LaunchCfg &lc);
+hipError_t launch_init(int lat, int storage, int eq, int fo, const double *rho, const double *u,
+                       const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
+                       const StepCoef &co, const LaunchCfg &lc);
+hipError_t launch_moments(int lat, int storage, const void *A, double *rho, double *u,
+                          double *theta, const GridDims &gd, const ForceDesc &fd,
+                          const StepCoef &co, const LaunchCfg &lc);
+hipError_t launch_heat_flux(int lat, int storage, int eq, int fo, const void *A, double *q,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc);
+hipError_t launch_totals(int lat, int storage, const void *A, double *partials, double *out_dev,
+                         const GridDims &gd, const StepCoef &co, hipStream_t stream);
+hipError_t launch_convert(int storage, const double *src, void *dst, int64_t n,
+                          hipStream_t stream);
+
+// Per-lattice / per-storage pieces, each explicitly instantiated in its own
+// translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
+template <int LAT, class S>
+hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
+                          const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
+template <int LAT>
+hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
+                         const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
+                         const StepCoef &co, const LaunchCfg &lc);
+template <int LAT>
+hipError_t launch_moments_l(int storage, const void *A, double *rho, double *u, double *theta,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc);
+template <int LAT>
+hipError_t launch_heat_flux_l(int storage, int eq, int fo, const void *A, double *q,
+                              const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                              const LaunchCfg &lc);
+template <int LAT>
+hipError_t launch_totals_l(int storage, const void *A, double *partials, double *out_dev,
+                           const GridDims &gd, const StepCoef &co, hipStream_t stream);
+
+constexpr int TOTALS_BLOCKS = 512;  // fixed partition: results independent of launch shape
+
+}  // namespace lbm

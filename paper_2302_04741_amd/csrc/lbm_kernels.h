@@ -1,0 +1,380 @@
+// HIP kernel templates of the gfx950 thermal LBM library.
+//
+//   step_kernel      one fused time step of eq. (lbm) (Li & Shan, arXiv:2302.04741,
+//                    Sec. 2): pull streaming, moments, mid-point values,
+//                    sigma-bar, Hermite equilibrium, Hermite force eq. (fi), BGK
+//                    relaxation, store.  One thread per cell, SoA populations.
+//   init_kernel      f~ = f0 - F/2 at step 0 (sigma = 0), written in pull layout.
+//   moments_kernel   physical rho, u + g/2, theta in FP64.
+//   heatflux_kernel  q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical f.
+//   totals kernels   FP64 sums of the stored populations in a fixed order.
+//
+// Layout: populations are SoA planes, A[i*N + cell], cell = (z*ny + y)*nx + x,
+// holding the deviations h_i = f~_i - w_i rho0 (scaled by 2^k_i for F16).
+// The stored state is post-collision ("pull" layout): the pre-collision value
+// of velocity i at cell x is A[i*N + (x - c_i mod L)].  A step reads every
+// element of A exactly once (a permutation per plane) and writes every element
+// of B exactly once, at the thread's own cell.
+#pragma once
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// storage codecs: S = stored type, T = arithmetic type; both sides are h_i
+// ---------------------------------------------------------------------------
+template <class S> struct ArithOf;
+template <> struct ArithOf<double> { using type = double; };
+template <> struct ArithOf<float> { using type = float; };
+template <> struct ArithOf<__half> { using type = float; };
+
+template <class L, class S> struct Codec {
+    template <int I, class T> __device__ static __forceinline__ T load(S v) { return T(v); }
+    template <int I, class T> __device__ static __forceinline__ S store(T h) { return S(h); }
+};
+
+// F16 deviations: stored value h_i 2^k_i, k_i = round(-log2 w_i).
+template <class L> struct Codec<L, __half> {
+    template <int I> static constexpr double scale()
+    {
+        double s = 1.0;
+        for (int e = 0; e < DevScale<L>::k(I); ++e) s *= 2.0;
+        return s;
+    }
+    template <int I, class T> __device__ static __forceinline__ T load(__half v)
+    {
+        return T(__half2float(v)) * T(1.0 / scale<I>());
+    }
+    template <int I, class T> __device__ static __forceinline__ __half store(T h)
+    {
+        return __float2half_rn(float(h * T(scale<I>())));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// pull gather: h_i = A[i][x - c_i (periodic)]
+// ---------------------------------------------------------------------------
+template <class L, class S, class T>
+__device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &gd, int x, int y,
+                                       int z, T (&h)[L::Q])
+{
+    int xs[7], ys[7], zs[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        xs[d] = wrap3(x - (d - 3), gd.nx);
+        ys[d] = wrap3(y - (d - 3), gd.ny);
+        zs[d] = (L::D == 3) ? wrap3(z - (d - 3), gd.nz) : 0;
+    }
+    const int64_t N = gd.N;
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+        const int64_t row = (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx;
+        const S *plane = A + int64_t(i) * N + row;
+        h[i] = Codec<L, S>::template load<i, T>(plane[xs[cx + 3]]);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// K1: fused step
+// ---------------------------------------------------------------------------
+// Largest block of the step kernel: FP64 arithmetic needs more than 128 VGPRs
+// per lane, so its blocks stay at 256 threads (4 waves).
+template <class S> constexpr int step_max_threads()
+{
+    return sizeof(typename ArithOf<S>::type) == 8 ? 256 : 1024;
+}
+
+template <int LAT, class S, int EQ, int FO>
+__global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__restrict__ A,
+                                                                     S *__restrict__ B,
+                                                                     GridDims gd, ForceDesc fd,
+                                                                     StepCoef co)
+{
+    using L = Lattice<LAT>;
+    using T = typename ArithOf<S>::type;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= gd.nx) return;
+    const int64_t N = gd.N;
+    const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
+
+    T h[L::Q];
+    gather<L, S, T>(A, gd, x, y, z, h);
+    T g[3];
+    load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
+
+    const RawSums<T> rs = raw_sums<L, T>(h);
+    CellState<T> cs;
+    finish_moments<L, T, FO == 4>(rs, g, T(co.cf), T(co.rho0), cs);
+
+    // h* = h + om (f0 - f) + cf F with f0 - f = w drho + (f0 - w rho) - h:
+    //    = h + fma(om, fma(w, drho, -h), [om (f0 - w rho) + cf F]).
+    // The bracket is what combo_pairs returns with NO_BASE (even +- odd part);
+    // every term is a small deviation, so the rounding stays at the size of h.
+    const T om = T(co.om);
+    const T drho = cs.drho;
+    S *__restrict__ out = B + cell;
+    combo_pairs<L, T, EQ, FO, true>(cs, om, T(co.cf), [&](auto IP, auto IM, T ev, T od) {
+        constexpr int ip = decltype(IP)::value;
+        constexpr int im = decltype(IM)::value;
+        constexpr double w = L::wshell(L::shell(ip));
+        const T dp = __builtin_fma(T(w), drho, -h[ip]);
+        out[int64_t(ip) * N] =
+            Codec<L, S>::template store<ip, T>(h[ip] + __builtin_fma(om, dp, ev + od));
+        if constexpr (im >= 0) {
+            const T dm = __builtin_fma(T(w), drho, -h[im]);
+            out[int64_t(im) * N] =
+                Codec<L, S>::template store<im, T>(h[im] + __builtin_fma(om, dm, ev - od));
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// runtime-storage access for the kernels off the step path
+// (storage: 0 = double, 1 = float, 2 = F16 deviations); all values are h_i
+// ---------------------------------------------------------------------------
+template <class L, int I>
+__device__ __forceinline__ double load_any(const void *A, int storage, int64_t idx)
+{
+    if (storage == 0) return static_cast<const double *>(A)[idx];
+    if (storage == 1) return double(static_cast<const float *>(A)[idx]);
+    return Codec<L, __half>::template load<I, double>(static_cast<const __half *>(A)[idx]);
+}
+
+template <class L, int I>
+__device__ __forceinline__ void store_any(void *A, int storage, int64_t idx, double h)
+{
+    if (storage == 0) static_cast<double *>(A)[idx] = h;
+    else if (storage == 1) static_cast<float *>(A)[idx] = float(h);
+    else static_cast<__half *>(A)[idx] = Codec<L, __half>::template store<I, double>(h);
+}
+
+template <class L>
+__device__ __forceinline__ void gather_any(const void *A, int storage, const GridDims &gd, int x,
+                                           int y, int z, double (&h)[L::Q])
+{
+    int xs[7], ys[7], zs[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        xs[d] = wrap3(x - (d - 3), gd.nx);
+        ys[d] = wrap3(y - (d - 3), gd.ny);
+        zs[d] = (L::D == 3) ? wrap3(z - (d - 3), gd.nz) : 0;
+    }
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+        const int64_t idx =
+            int64_t(i) * gd.N + (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx + xs[cx + 3];
+        h[i] = load_any<L, i>(A, storage, idx);
+    });
+}
+
+__device__ __forceinline__ void force_any(const ForceDesc &fd, int storage, const GridDims &gd,
+                                          int D, int x, int y, int z, int64_t cell, double g[3])
+{
+    if (storage == 0) {
+        if (D == 2) load_force<double, double, 2>(fd, gd, x, y, z, cell, g);
+        else load_force<double, double, 3>(fd, gd, x, y, z, cell, g);
+    } else {
+        if (D == 2) load_force<float, double, 2>(fd, gd, x, y, z, cell, g);
+        else load_force<float, double, 3>(fd, gd, x, y, z, cell, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: initial state f~ = f0 - F/2 (sigma = 0), computed in FP64, stored as
+// h = f~ - w rho0 and scattered so that the pull gather of the first step
+// finds h_i(x) at A[i][x - c_i].
+// ---------------------------------------------------------------------------
+template <int LAT, int EQ, int FO>
+__global__ void __launch_bounds__(256)
+    init_kernel(const double *__restrict__ rho, const double *__restrict__ u,
+                const double *__restrict__ theta, void *__restrict__ A, int storage, GridDims gd,
+                ForceDesc fd, StepCoef co)
+{
+    using L = Lattice<LAT>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= gd.nx) return;
+    const int64_t N = gd.N;
+    const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
+
+    double g[3];
+    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
+    CellState<double> cs;
+    cs.rho = rho[cell];
+    cs.drho = cs.rho - co.rho0;
+    cs.th = theta[cell];
+    for (int a = 0; a < 3; ++a) {
+        cs.ub[a] = (a < L::D) ? u[int64_t(a) * N + cell] : 0.0;
+        cs.g[a] = g[a];
+        for (int b = 0; b < 3; ++b) cs.sig[a][b] = 0.0;
+    }
+    constexpr int FOI = FO == 4 ? 3 : FO;  // sigma = 0 at the start
+    // h = w (rho - rho0) + (f0 - w rho) - F/2
+    combo_pairs<L, double, EQ, FOI, true>(cs, 1.0, -0.5, [&](auto IP, auto IM, double ev,
+                                                            double od) {
+        constexpr int ip = decltype(IP)::value;
+        constexpr int im = decltype(IM)::value;
+        constexpr double w = L::wshell(L::shell(ip));
+        auto put = [&](auto II, double v) {
+            constexpr int i = decltype(II)::value;
+            const int xd = wrap3(x - L::c(i, 0), gd.nx);
+            const int yd = wrap3(y - L::c(i, 1), gd.ny);
+            const int zd = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
+            const int64_t dst = (int64_t(zd) * gd.ny + yd) * gd.nx + xd;
+            store_any<L, i>(A, storage, int64_t(i) * N + dst, v);
+        };
+        const double base = w * cs.drho;
+        put(std::integral_constant<int, ip>{}, base + (ev + od));
+        if constexpr (im >= 0) put(std::integral_constant<int, im>{}, base + (ev - od));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// K3: physical moments (FP64)
+// ---------------------------------------------------------------------------
+template <int LAT>
+__global__ void __launch_bounds__(256)
+    moments_kernel(const void *__restrict__ A, int storage, double *__restrict__ rho,
+                   double *__restrict__ u, double *__restrict__ theta, GridDims gd, ForceDesc fd,
+                   StepCoef co)
+{
+    using L = Lattice<LAT>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= gd.nx) return;
+    const int64_t N = gd.N;
+    const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
+    double h[L::Q];
+    gather_any<L>(A, storage, gd, x, y, z, h);
+    double g[3];
+    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
+    const RawSums<double> rs = raw_sums<L, double>(h);
+    CellState<double> cs;
+    finish_moments<L, double, false>(rs, g, co.cf, co.rho0, cs);
+    if (rho) rho[cell] = cs.rho;
+    if (theta) theta[cell] = cs.th;
+    if (u)
+        for (int a = 0; a < L::D; ++a) u[int64_t(a) * N + cell] = cs.ub[a];
+}
+
+// ---------------------------------------------------------------------------
+// K5: heat flux of the physical distribution (FP64)
+//   f = f0 + cf (f~ - f0 + F/2) = cf f~ + (1 - cf) f0 + (cf/2) F
+//     = w rho0 + cf h + (1 - cf) w drho + [(1 - cf)(f0 - w rho) + (cf/2) F]
+// ---------------------------------------------------------------------------
+template <int LAT, int EQ, int FO>
+__global__ void __launch_bounds__(256)
+    heatflux_kernel(const void *__restrict__ A, int storage, double *__restrict__ q, GridDims gd,
+                    ForceDesc fd, StepCoef co)
+{
+    using L = Lattice<LAT>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= gd.nx) return;
+    const int64_t N = gd.N;
+    const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
+    double h[L::Q];
+    gather_any<L>(A, storage, gd, x, y, z, h);
+    double g[3];
+    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
+    const RawSums<double> rs = raw_sums<L, double>(h);
+    CellState<double> cs;
+    finish_moments<L, double, FO == 4>(rs, g, co.cf, co.rho0, cs);
+    const double cf = co.cf;
+    double qa[3] = {0.0, 0.0, 0.0};
+    auto acc = [&](auto II, double fp) {
+        constexpr int i = decltype(II)::value;
+        double cv[3], cc = 0.0;
+        for (int a = 0; a < L::D; ++a) {
+            cv[a] = L::R * double(L::c(i, a)) - cs.ub[a];
+            cc += cv[a] * cv[a];
+        }
+        for (int a = 0; a < L::D; ++a) qa[a] += fp * cc * cv[a];
+    };
+    combo_pairs<L, double, EQ, FO, true>(
+        cs, 1.0 - cf, 0.5 * cf, [&](auto IP, auto IM, double ev, double od) {
+            constexpr int ip = decltype(IP)::value;
+            constexpr int im = decltype(IM)::value;
+            constexpr double w = L::wshell(L::shell(ip));
+            const double base = w * co.rho0 + (1.0 - cf) * w * cs.drho;
+            acc(IP, base + cf * h[ip] + (ev + od));
+            if constexpr (im >= 0) acc(IM, base + cf * h[im] + (ev - od));
+        });
+    for (int a = 0; a < L::D; ++a) q[int64_t(a) * N + cell] = 0.5 * qa[a];
+}
+
+// ---------------------------------------------------------------------------
+// K4: totals.  Stage 1: block b sums a fixed slice of every population plane
+// of h; stage 2: one block adds the slices in order and forms the moments of
+// f = w rho0 + h using sum w = 1, sum w c = 0 and sum w |c|^2 r^2 = D:
+//   mass = N rho0 + sum H_i, momentum = r sum c_i H_i,
+//   energy = N rho0 D + r^2 sum |c_i|^2 H_i,  with H_i = sum_x h_i(x).
+// The partition and the reduction order do not depend on the grid or launch
+// shape of the step, so the result is bitwise reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_256(double v, double *lds)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+template <int LAT>
+__global__ void __launch_bounds__(256)
+    totals_stage1(const void *__restrict__ A, int storage, double *__restrict__ partials,
+                  GridDims gd)
+{
+    using L = Lattice<LAT>;
+    __shared__ double lds[4];
+    const int64_t N = gd.N;
+    const int64_t chunk = (N + TOTALS_BLOCKS - 1) / TOTALS_BLOCKS;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = (lo + chunk < N) ? lo + chunk : N;
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        double v = 0.0;
+        for (int64_t k = lo + threadIdx.x; k < hi; k += 256)
+            v += load_any<L, i>(A, storage, int64_t(i) * N + k);
+        v = block_sum_256(v, lds);
+        if (threadIdx.x == 0) partials[int64_t(blockIdx.x) * L::Q + i] = v;
+    });
+}
+
+template <int LAT>
+__global__ void __launch_bounds__(256) totals_stage2(const double *__restrict__ partials,
+                                                     double *__restrict__ out, GridDims gd,
+                                                     StepCoef co)
+{
+    using L = Lattice<LAT>;
+    __shared__ double lds[4];
+    __shared__ double Hi[L::Q];
+    for (int i = 0; i < L::Q; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < TOTALS_BLOCKS; b += 256) v += partials[int64_t(b) * L::Q + i];
+        v = block_sum_256(v, lds);
+        if (threadIdx.x == 0) Hi[i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0, p[3] = {0.0, 0.0, 0.0}, e = 0.0;
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            m += Hi[i];
+            for (int a = 0; a < L::D; ++a) p[a] += double(L::c(i, a)) * Hi[i];
+            e += double(c2<L>(i)) * Hi[i];
+        });
+        const double base = double(gd.N) * co.rho0;
+        out[0] = base + m;
+        for (int a = 0; a < L::D; ++a) out[1 + a] = L::R * p[a];
+        out[1 + L::D] = base * double(L::D) + L::R2 * e;
+    }
+}
+
+}  // namespace lbm

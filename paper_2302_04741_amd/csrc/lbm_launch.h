@@ -1,0 +1,99 @@
+// Launcher templates: included by the per-lattice translation units, which
+// instantiate them explicitly.
+#pragma once
+
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+inline dim3 cell_grid(const GridDims &gd, int bx)
+{
+    return dim3(unsigned((gd.nx + bx - 1) / bx), unsigned(gd.ny), unsigned(gd.nz));
+}
+
+// Threads per block along x: the requested count, at most nx rounded up to a
+// whole wavefront.
+inline int block_for(const GridDims &gd, int want)
+{
+    const int b = want > 0 ? want : 256;
+    const int nx64 = ((gd.nx + 63) / 64) * 64;
+    return b < nx64 ? b : nx64;
+}
+
+template <int LAT, class F> hipError_t with_eq_fo(int eq, int fo, F &&f)
+{
+    hipError_t r = hipErrorInvalidValue;
+    static_for<2, Lattice<LAT>::MAXEQ + 1>([&](auto E) {
+        static_for<1, 5>([&](auto O) {
+            if (eq == decltype(E)::value && fo == decltype(O)::value) r = f(E, O);
+        });
+    });
+    return r;
+}
+
+template <int LAT, class S>
+hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
+                          const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
+{
+    int bx = block_for(gd, lc.block);
+    bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        hipLaunchKernelGGL((step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, static_cast<const S *>(A),
+                           static_cast<S *>(B), gd, fd, co);
+        return hipGetLastError();
+    });
+}
+
+template <int LAT>
+hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
+                         const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
+                         const StepCoef &co, const LaunchCfg &lc)
+{
+    const int bx = block_for(gd, 256);
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        hipLaunchKernelGGL((init_kernel<LAT, decltype(E)::value, decltype(O)::value>),
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, rho, u, theta, A, storage,
+                           gd, fd, co);
+        return hipGetLastError();
+    });
+}
+
+template <int LAT>
+hipError_t launch_moments_l(int storage, const void *A, double *rho, double *u, double *theta,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc)
+{
+    const int bx = block_for(gd, 256);
+    hipLaunchKernelGGL((moments_kernel<LAT>), cell_grid(gd, bx), dim3(bx), 0, lc.stream, A,
+                       storage, rho, u, theta, gd, fd, co);
+    return hipGetLastError();
+}
+
+template <int LAT>
+hipError_t launch_heat_flux_l(int storage, int eq, int fo, const void *A, double *q,
+                              const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                              const LaunchCfg &lc)
+{
+    const int bx = block_for(gd, 256);
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        hipLaunchKernelGGL((heatflux_kernel<LAT, decltype(E)::value, decltype(O)::value>),
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, A, storage, q, gd, fd, co);
+        return hipGetLastError();
+    });
+}
+
+template <int LAT>
+hipError_t launch_totals_l(int storage, const void *A, double *partials, double *out_dev,
+                           const GridDims &gd, const StepCoef &co, hipStream_t stream)
+{
+    hipLaunchKernelGGL((totals_stage1<LAT>), dim3(TOTALS_BLOCKS), dim3(256), 0, stream, A,
+                       storage, partials, gd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((totals_stage2<LAT>), dim3(1), dim3(256), 0, stream, partials, out_dev,
+                       gd, co);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

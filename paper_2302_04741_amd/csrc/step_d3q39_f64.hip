@@ -1,0 +1,8 @@
+// Fused step kernels for D3Q39 with double storage (all equilibrium and force orders).
+#include "lbm_launch.h"
+
+namespace lbm {
+template hipError_t launch_step_ls<1, double>(int, int, const void *, void *, const GridDims &,
+                                               const ForceDesc &, const StepCoef &,
+                                               const LaunchCfg &);
+}  // namespace lbm

@@ -1,0 +1,210 @@
+"""Python handle over the C ABI: torch supplies device memory and streams.
+
+Every step of the method runs in the HIP kernels of liblbm.so; this module only
+allocates the workspace and the in/out tensors with torch and passes pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import LATTICES, check, load
+
+DIM = {"D2Q37": 2, "D3Q39": 3}
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("a ROCm GPU is required: the library has no CPU path")
+    return torch
+
+
+def _as_device(torch, a, shape, device, stream, keep):
+    """float64 contiguous device tensor of `shape` from a tensor or array."""
+    if isinstance(a, torch.Tensor) and a.is_cuda:
+        t = a.to(device=device, dtype=torch.float64).reshape(shape).contiguous()
+    else:
+        arr = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape))
+        t = torch.from_numpy(arr.copy()).to(device=device, non_blocking=False)
+    if t.data_ptr() != getattr(a, "data_ptr", lambda: None)():
+        # a temporary owned here: keep it alive until the stream has used it
+        t.record_stream(stream)
+    keep.append(t)
+    return t
+
+
+class Sim:
+    """One periodic simulation whose populations live in a torch-owned workspace.
+
+    lattice: "D2Q37" or "D3Q39"; dims: (nx, ny[, nz]); tau_hat: relaxation time
+    of eq. (lbm); rho, theta: (N,), u: (D, N) initial fields (numpy or torch, any
+    device; converted to FP64 on the GPU); cell = (z*ny + y)*nx + x.
+    storage: "f64" | "f32" (| "f16dev"); eq_order: 0 = highest supported;
+    force_order: 1..4 (4 = full scheme incl. a3_F and sigma); rho0: reference
+    density of the stored deviations (default 1; 0 stores f~ itself).
+    """
+
+    def __init__(self, lattice: str, dims, tau_hat: float, rho, u, theta, *, storage="f64",
+                 eq_order: int = 0, force_order: int = 4, force_field: bool = False,
+                 rho0: float | None = None, device=None, stream=None):
+        torch = _torch()
+        L = load()
+        self.lattice = lattice
+        self.D = DIM[lattice]
+        nx, ny, nz = (tuple(int(d) for d in dims) + (1, 1))[:3]
+        self.dims = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.storage = storage
+        if rho0 is None:
+            # store deviations from w_i * 1 (rho0 = 0 gives the literal form)
+            rho0 = 1.0
+        self.rho0 = rho0
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = _lib.make_params(lattice, self.dims, tau_hat, storage, eq_order,
+                                       force_order, force_field, rho0)
+        nbytes = L.lbm_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            # invalid parameters: let lbm_create report why
+            nbytes = 256
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.workspace_bytes = nbytes
+        self._ws_ptr = raw.data_ptr() + off
+        keep = []
+        N, D = self.N, self.D
+        with torch.cuda.stream(self.stream):
+            r = _as_device(torch, rho, (N,), self.device, self.stream, keep)
+            uu = _as_device(torch, u, (D, N), self.device, self.stream, keep)
+            th = _as_device(torch, theta, (N,), self.device, self.stream, keep)
+        handle = ctypes.c_void_p()
+        check(L.lbm_create(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
+                           ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                           ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(uu.data_ptr()),
+                           ctypes.c_void_p(th.data_ptr()), ctypes.byref(handle)))
+        self._h = handle
+        del keep  # temporaries are protected by record_stream until the stream has used them
+
+    # -- helpers -------------------------------------------------------------
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("simulation is closed")
+        return self._h
+
+    def _empty(self, *shape):
+        torch = _torch()
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    # -- the five calls ------------------------------------------------------
+    def set_force(self, g=None, *, axis=None, profile=None, field=None):
+        """Uniform g (D values), an axis profile (D, L_axis) along `axis`, or a
+        full (D, N) field."""
+        torch = _torch()
+        L = load()
+        if g is not None:
+            gg = (ctypes.c_double * 3)(*[float(v) for v in np.asarray(g, np.float64).reshape(-1)[:self.D]])
+            check(L.lbm_set_force(self.handle, 0, gg, 0, 0))
+            return
+        keep = []
+        with torch.cuda.stream(self.stream):
+            self._set_force_device(torch, L, keep, axis, profile, field)
+
+    def _set_force_device(self, torch, L, keep, axis, profile, field):
+        if profile is not None:
+            prof = np.asarray(profile.cpu() if isinstance(profile, torch.Tensor) else profile,
+                              dtype=np.float64).reshape(self.D, -1)
+            t = _as_device(torch, prof, prof.shape, self.device, self.stream, keep)
+            check(L.lbm_set_force(self.handle, 1, ctypes.c_void_p(t.data_ptr()), int(axis),
+                                  prof.shape[1]))
+        elif field is not None:
+            t = _as_device(torch, field, (self.D, self.N), self.device, self.stream, keep)
+            check(L.lbm_set_force(self.handle, 2, ctypes.c_void_p(t.data_ptr()), 0, 0))
+        else:
+            raise ValueError("give g, profile= (with axis=) or field=")
+
+    def set_workload_force(self, force):
+        """Apply a workload force tuple: ("uniform", g) | ("axis", axis, prof) | ("field", g)."""
+        kind = force[0]
+        if kind == "uniform":
+            self.set_force(force[1])
+        elif kind == "axis":
+            self.set_force(axis=force[1], profile=force[2])
+        elif kind == "field":
+            self.set_force(field=force[1])
+        else:
+            raise ValueError(kind)
+
+    def step(self, n: int = 1):
+        check(load().lbm_step(self.handle, int(n)))
+
+    def moments(self):
+        """(rho (N,), u (D, N), theta (N,)) as float64 device tensors."""
+        rho, u, th = self._empty(self.N), self._empty(self.D, self.N), self._empty(self.N)
+        check(load().lbm_moments(self.handle, ctypes.c_void_p(rho.data_ptr()),
+                                 ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(th.data_ptr())))
+        return rho, u, th
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lbm_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- diagnostics -----------------------------------------------------------
+    def heat_flux(self):
+        q = self._empty(self.D, self.N)
+        check(load().lbm_heat_flux(self.handle, ctypes.c_void_p(q.data_ptr())))
+        return q
+
+    def totals(self) -> np.ndarray:
+        out = (ctypes.c_double * (self.D + 2))()
+        check(load().lbm_totals(self.handle, out))
+        return np.array(out[:])
+
+    def population_bytes(self) -> int:
+        return int(load().lbm_population_bytes(self.handle))
+
+    def get_populations(self):
+        torch = _torch()
+        t = torch.empty(self.population_bytes(), dtype=torch.uint8, device=self.device)
+        check(load().lbm_get_populations(self.handle, ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def set_populations(self, t):
+        assert t.numel() * t.element_size() == self.population_bytes()
+        check(load().lbm_set_populations(self.handle, ctypes.c_void_p(t.data_ptr())))
+
+    @property
+    def step_count(self) -> int:
+        return int(load().lbm_step_count(self.handle))
+
+    @step_count.setter
+    def step_count(self, n: int):
+        check(load().lbm_set_step_count(self.handle, int(n)))
+
+    def set_block(self, threads: int):
+        check(load().lbm_set_block(self.handle, int(threads)))
+
+    def set_stream(self, stream):
+        check(load().lbm_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+
+def from_workload(wl, storage="f64", **kw) -> Sim:
+    """Create a Sim for a workloads.Workload and apply its force."""
+    force_field = wl.force[0] == "field"
+    s = Sim(wl.lattice, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, storage=storage,
+            eq_order=wl.eq_order, force_order=wl.force_order, force_field=force_field, **kw)
+    s.set_workload_force(wl.force)
+    return s

@@ -1,0 +1,107 @@
+"""Bitwise determinism, checkpoint/resume and launch-shape independence (GPU).
+
+The step has no atomics and no cross-thread reductions, so every launch shape
+must give the same bits, and exporting/importing the populations must resume a
+run bitwise.  The totals use a fixed partition and order, so they repeat
+bitwise too.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2302_04741_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    from paper_2302_04741_amd import sim
+
+    return sim
+
+
+@pytest.mark.parametrize("lat,dims,storage", [("D2Q37", (200, 9, 1), "f64"),
+                                              ("D3Q39", (130, 6, 5), "f32")])
+def test_block_shape_does_not_change_bits(sim_mod, lat, dims, storage):
+    wl = workloads.random_smooth(lat, dims, seed=2, force_kind="axis", g_amp=1e-3)
+    pops = []
+    for block in (64, 128, 256, 1024):
+        s = sim_mod.from_workload(wl, storage=storage)
+        s.set_block(block)
+        s.step(7)
+        pops.append(s.get_populations().cpu())
+        s.close()
+    for p in pops[1:]:
+        assert torch.equal(p, pops[0])
+
+
+def test_resume_from_checkpoint_is_bitwise(sim_mod):
+    wl = workloads.random_smooth("D3Q39", (12, 10, 8), seed=3, force_kind="uniform", g_amp=1e-3)
+    a = sim_mod.from_workload(wl, storage="f32")
+    a.step(9)
+    ref = a.get_populations().clone()
+    b = sim_mod.from_workload(wl, storage="f32")
+    b.step(4)
+    ck = b.get_populations().clone()
+    c = sim_mod.from_workload(wl, storage="f32")
+    c.set_populations(ck)
+    c.step_count = 4
+    c.step(5)
+    assert c.step_count == 9
+    assert torch.equal(c.get_populations(), ref)
+
+
+def test_nan_canary_every_output_written(sim_mod):
+    wl = workloads.random_smooth("D2Q37", (67, 7, 1), seed=5, force_kind="uniform")
+    s = sim_mod.from_workload(wl)
+    s.step(1)
+    # fill the state with NaN, then restore a valid state and step: every
+    # element of the output buffer must be overwritten by finite values
+    good = s.get_populations().clone()
+    bad = torch.full_like(good.view(torch.float64), float("nan")).view(torch.uint8)
+    s.set_populations(bad)
+    s.step(1)  # writes the other buffer from NaN input: all NaN
+    s.set_populations(good)
+    s.step(1)
+    p = s.get_populations().view(torch.float64)
+    assert torch.isfinite(p).all()
+
+
+def test_totals_repeat_bitwise(sim_mod):
+    wl = workloads.random_smooth("D3Q39", (20, 9, 7), seed=6, force_kind="uniform")
+    s = sim_mod.from_workload(wl)
+    s.step(3)
+    t1 = s.totals()
+    t2 = s.totals()
+    assert np.array_equal(t1, t2)
+
+
+def test_nonfinite_state_is_reported(sim_mod):
+    from paper_2302_04741_amd._lib import LBM_ENONFINITE, LbmError
+
+    wl = workloads.random_smooth("D2Q37", (16, 16, 1), seed=7, force_kind="uniform")
+    s = sim_mod.from_workload(wl)
+    bad = torch.full((s.population_bytes() // 8,), float("inf"), dtype=torch.float64,
+                     device="cuda")
+    s.set_populations(bad.view(torch.uint8))
+    with pytest.raises(LbmError) as ei:
+        s.totals()
+    assert ei.value.status == LBM_ENONFINITE
+
+
+def test_force_errors_on_gpu(sim_mod):
+    from paper_2302_04741_amd._lib import LBM_EINVAL, LbmError
+
+    s = sim_mod.Sim("D2Q37", (8, 6), 0.8, 1.0, np.zeros((2, 48)), 1.0)
+    with pytest.raises(LbmError) as ei:
+        s.set_force(field=np.zeros((2, 48)))  # no LBM_FLAG_FORCE_FIELD at creation
+    assert ei.value.status == LBM_EINVAL
+    with pytest.raises(LbmError):
+        s.set_force(axis=0, profile=np.zeros((2, 7)))  # length 7 != nx = 8
+    with pytest.raises(LbmError):
+        s.set_force(axis=2, profile=np.zeros((2, 1)))  # no z axis in 2-D
+    with pytest.raises(LbmError):
+        s.set_force([float("nan"), 0.0])
+    with pytest.raises(LbmError):
+        s.set_block(96)

@@ -1,0 +1,108 @@
+"""Full-size checks of the benchmark workloads, in the launch configuration the
+benchmark times (default block shape, deviation storage).
+
+* Sampled parity: after a few steps, the moments at sampled cells (corners
+  included, so the periodic wrap is exercised) are recomputed one by one by the
+  oracle on a periodic window of half-width 3*steps + 1 around each cell
+  (information travels at most 3 nodes per step, so the window edge cannot reach
+  the centre).  Errors are relative to the maxima of the initial fields.
+* Properties at any size after the full run length: mass conserved, momentum
+  grows by n * M * g for a uniform force, fields stay finite.
+"""
+import numpy as np
+import pytest
+
+from _parity import gpu_moments, oracle_window_moments
+from paper_2302_04741_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = (1e-12, 1e-12, 1e-12)
+# a few FP32 steps: rounding of the stored deviations (eps32 = 6e-8) only
+TOL32 = (2e-6, 5e-5, 2e-6)
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    from paper_2302_04741_amd import sim
+
+    return sim
+
+
+@pytest.fixture(scope="module")
+def kolmogorov256():
+    wl = workloads.kolmogorov_3d(n=256)
+    return wl, wl.force_field()
+
+
+def sampled_check(sim_mod, oracle_mod, wl, g_field, storage, steps, samples, tol):
+    s = sim_mod.from_workload(wl, storage=storage)
+    s.step(steps)
+    rho, u, th = gpu_moments(s)
+    s.close()
+    nx, ny, nz = wl.dims
+    umax = np.sqrt((wl.u ** 2).sum(axis=0)).max()
+    worst = np.zeros(3)
+    for (x, y, z) in samples:
+        cell = (z * ny + y) * nx + x
+        r_o, u_o, t_o = oracle_window_moments(oracle_mod, wl, (x, y, z), steps, g_field)
+        e = np.array([abs(rho[cell] - r_o) / np.abs(wl.rho).max(),
+                      np.sqrt(((u[:, cell] - u_o) ** 2).sum()) / umax,
+                      abs(th[cell] - t_o) / np.abs(wl.theta).max()])
+        worst = np.maximum(worst, e)
+    print("%s %s %d steps, %d samples: worst rho %.2e u %.2e theta %.2e"
+          % (wl.name, storage, steps, len(samples), *worst), flush=True)
+    assert np.all(np.isfinite(rho)) and np.all(np.isfinite(th))
+    assert all(w <= t for w, t in zip(worst, tol)), worst
+
+
+SAMPLES_3D = [(0, 0, 0), (255, 255, 255), (128, 37, 200), (3, 250, 131), (77, 128, 1),
+              (254, 3, 66), (200, 200, 254)]
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", TOL32), ("f64", TOL64)])
+def test_kolmogorov_256cube_sampled(sim_mod, oracle_mod, kolmogorov256, storage, tol):
+    wl, g = kolmogorov256
+    sampled_check(sim_mod, oracle_mod, wl, g, storage, 4, SAMPLES_3D, tol)
+
+
+SAMPLES_2D = [(0, 0, 0), (1023, 1023, 0), (512, 3, 0), (5, 700, 0), (999, 256, 0)]
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", TOL32), ("f64", TOL64)])
+@pytest.mark.parametrize("force_order", [4, 2])
+def test_thermal_shear_1024_sampled(sim_mod, oracle_mod, storage, tol, force_order):
+    wl = workloads.thermal_shear_2d(n=1024, tau_hat=0.6, dtheta=0.1, mach=0.2,
+                                    force_order=force_order)
+    sampled_check(sim_mod, oracle_mod, wl, wl.force_field(), storage, 5, SAMPLES_2D, tol)
+
+
+@pytest.mark.parametrize("force_order", [4, 2])
+def test_thermal_shear_1024_5000_steps_conservation(sim_mod, force_order):
+    wl = workloads.thermal_shear_2d(n=1024, tau_hat=0.9, dtheta=0.1, mach=0.2,
+                                    force_order=force_order)
+    s = sim_mod.from_workload(wl, storage="f64")
+    t0 = s.totals()
+    s.step(5000)
+    t1 = s.totals()
+    M = t0[0]
+    assert abs(t1[0] - M) <= 1e-12 * M
+    g = np.asarray(wl.force[1])
+    # sum_x rho g per step with a uniform g: n M g exactly
+    np.testing.assert_allclose(t1[1:3] - t0[1:3], 5000 * M * g, rtol=1e-9, atol=1e-9 * M)
+    rho, u, th = gpu_moments(s)
+    assert np.all(np.isfinite(u)) and np.all(th > 0)
+
+
+def test_kolmogorov_256cube_2000_steps_fp32(sim_mod, kolmogorov256):
+    wl, _ = kolmogorov256
+    s = sim_mod.from_workload(wl, storage="f32")
+    t0 = s.totals()
+    s.step(2000)
+    t1 = s.totals()
+    # FP32 rounding of every stored deviation each step: mass drifts by a
+    # random walk of ~sqrt(2000) * 1e-7 relative at most
+    assert abs(t1[0] - t0[0]) <= 1e-5 * t0[0]
+    rho, u, th = gpu_moments(s)
+    assert np.all(np.isfinite(u)) and np.abs(u).max() < 0.1
+    assert np.abs(rho - 1).max() < 0.1 and np.abs(th - 1).max() < 0.1

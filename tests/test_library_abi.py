@@ -1,0 +1,190 @@
+"""The C-ABI library on the host: it loads, exports every symbol include/lbm.h
+declares, validates arguments before touching the GPU, and compiles in the same
+quadrature rules the oracle derives independently (CPU only; no compute call)."""
+import ctypes
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_04741_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2302_04741_amd import build
+
+        build.build()
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return re.findall(r"^LBM_API[^(]*?\b(lbm_\w+)\(", text, flags=re.M)
+
+
+def test_header_declares_the_binding_api():
+    assert sorted(declared_symbols()) == sorted(_lib.API_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_only_declared_symbols_are_exported():
+    import subprocess
+
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert exported == set(declared_symbols())
+
+
+def test_version(lib):
+    assert lib.lbm_version().decode().startswith("lbm-gfx950")
+
+
+def params(**kw):
+    base = dict(lattice="D2Q37", dims=(64, 64, 1), tau_hat=0.8)
+    base.update(kw)
+    return _lib.make_params(**base)
+
+
+def create(lib, p, ws=0x100000, nbytes=None, fields=(0x200000, 0x300000, 0x400000)):
+    """lbm_create with fake (never dereferenced) device pointers."""
+    h = ctypes.c_void_p()
+    if nbytes is None:
+        nbytes = _lib.workspace_bytes(p) if p is not None else 0
+    pp = ctypes.byref(p) if p is not None else None
+    st = lib.lbm_create(pp, ctypes.c_void_p(ws), ctypes.c_size_t(nbytes), None,
+                        *[ctypes.c_void_p(f) if f else None for f in fields], ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(tau_hat=0.5), _lib.LBM_EINVAL),
+    (dict(tau_hat=0.3), _lib.LBM_EINVAL),
+    (dict(tau_hat=float("nan")), _lib.LBM_EINVAL),
+    (dict(dims=(0, 64, 1)), _lib.LBM_EINVAL),
+    (dict(dims=(64, -1, 1)), _lib.LBM_EINVAL),
+    (dict(dims=(64, 64, 2)), _lib.LBM_EINVAL),
+    (dict(dims=(64, 70000, 1)), _lib.LBM_EUNSUPPORTED),
+    (dict(eq_order=1), _lib.LBM_EINVAL),
+    (dict(eq_order=-1), _lib.LBM_EINVAL),
+    (dict(eq_order=5), _lib.LBM_EUNSUPPORTED),
+    (dict(lattice="D3Q39", dims=(8, 8, 8), eq_order=4), _lib.LBM_EUNSUPPORTED),
+    (dict(force_order=0), _lib.LBM_EINVAL),
+    (dict(force_order=5), _lib.LBM_EINVAL),
+    (dict(rho0=-1.0), _lib.LBM_EINVAL),
+    (dict(rho0=float("inf")), _lib.LBM_EINVAL),
+])
+def test_invalid_parameters(lib, kw, status):
+    p = params(**kw)
+    assert _lib.workspace_bytes(p) == 0
+    st, h = create(lib, p, nbytes=1 << 30)
+    assert st == status and not h.value
+    assert lib.lbm_last_error().decode() != ""
+
+
+def test_unknown_lattice_storage_and_struct_size(lib):
+    p = params()
+    p.lattice = 7
+    assert create(lib, p, nbytes=1 << 30)[0] == _lib.LBM_EINVAL
+    p = params()
+    p.storage = 9
+    assert create(lib, p, nbytes=1 << 30)[0] == _lib.LBM_EINVAL
+    p = params()
+    p.struct_size = 8
+    assert create(lib, p, nbytes=1 << 30)[0] == _lib.LBM_EINVAL
+    p = params()
+    p.flags = 0x80
+    assert create(lib, p, nbytes=1 << 30)[0] == _lib.LBM_EINVAL
+    assert lib.lbm_workspace_bytes(None) == 0
+    assert create(lib, None)[0] == _lib.LBM_EINVAL
+
+
+def test_workspace_and_field_checks(lib):
+    p = params()
+    need = _lib.workspace_bytes(p)
+    assert create(lib, p, ws=0)[0] == _lib.LBM_EINVAL
+    assert create(lib, p, ws=0x100010)[0] == _lib.LBM_EINVAL  # not 256-byte aligned
+    assert create(lib, p, nbytes=need - 1)[0] == _lib.LBM_ENOSPACE
+    assert create(lib, p, fields=(0, 0x300000, 0x400000))[0] == _lib.LBM_EINVAL
+    assert create(lib, p, fields=(0x200000, 0, 0x400000))[0] == _lib.LBM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(0x100000), need, None, None, None,
+                          None, None) == _lib.LBM_EINVAL
+
+
+@pytest.mark.parametrize("lattice,dims,storage,sbytes,Q,D", [
+    ("D2Q37", (64, 64, 1), "f64", 8, 37, 2),
+    ("D2Q37", (1024, 1024, 1), "f32", 4, 37, 2),
+    ("D3Q39", (256, 256, 256), "f32", 4, 39, 3),
+    ("D3Q39", (32, 32, 32), "f64", 8, 39, 3),
+])
+def test_workspace_size(lattice, dims, storage, sbytes, Q, D):
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    p = _lib.make_params(lattice, dims, 0.8, storage)
+    N = int(np.prod(dims))
+    abytes = 8 if storage == "f64" else 4
+    expect = 2 * up(Q * N * sbytes) + up(D * max(dims) * abytes) + up(512 * Q * 8) + up(64)
+    assert _lib.workspace_bytes(p) == expect
+    pf = _lib.make_params(lattice, dims, 0.8, storage, force_field=True)
+    expect_f = 2 * up(Q * N * sbytes) + up(D * N * abytes) + up(512 * Q * 8) + up(64)
+    assert _lib.workspace_bytes(pf) == expect_f
+
+
+def test_null_handle_calls(lib):
+    lib.lbm_destroy(None)  # no-op
+    assert lib.lbm_step(None, 1) == _lib.LBM_EINVAL
+    assert lib.lbm_moments(None, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_set_force(None, 0, None, 0, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_totals(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_heat_flux(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_get_populations(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_set_populations(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_set_step_count(None, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_set_block(None, 64) == _lib.LBM_EINVAL
+    assert lib.lbm_set_stream(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_count(None) == -1
+    assert lib.lbm_population_bytes(None) == 0
+    assert lib.lbm_lattice_table(5, None, None, None) == _lib.LBM_EINVAL
+
+
+@pytest.mark.parametrize("lattice,lat,deg", [("D2Q37", 0, 9), ("D3Q39", 1, 7)])
+def test_compiled_rule_is_gauss_hermite(lib, lattice, lat, deg):
+    c, w, r = _lib.lattice_table(lattice)
+    D = 2 if lat == 0 else 3
+    xi = r * c[:, :D].astype(np.float64)
+    for tot in range(deg + 1):
+        for p in itertools.product(range(tot + 1), repeat=D):
+            if sum(p) != tot:
+                continue
+            m = np.sum(w * np.prod(xi ** np.asarray(p), axis=1))
+            ref = 0.0 if any(k % 2 for k in p) else float(np.prod(
+                [np.prod(np.arange(k - 1, 0, -2)) if k else 1 for k in p]))
+            assert abs(m - ref) < 1e-13 * max(1, ref)
+    # velocities come as rest, then +c/-c pairs
+    assert np.all(c[0] == 0)
+    assert np.all(c[1::2] == -c[2::2])
+
+
+@pytest.mark.parametrize("lattice,lat", [("D2Q37", 0), ("D3Q39", 1)])
+def test_compiled_rule_equals_oracle_derivation(lib, oracle_mod, lattice, lat):
+    c, w, r = _lib.lattice_table(lattice)
+    oc, ow, orr, _ = oracle_mod.lattice(lat)
+    assert abs(r - orr) < 1e-15
+    mine = {tuple(v): wv for v, wv in zip(c, w)}
+    theirs = {tuple(v): wv for v, wv in zip(oc, ow)}
+    assert set(mine) == set(theirs)
+    for k in mine:
+        assert abs(mine[k] - theirs[k]) < 1e-16 * max(1.0, 10 * theirs[k])
