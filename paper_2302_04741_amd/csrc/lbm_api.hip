@@ -120,8 +120,9 @@ lbm_status check_params(const lbm_params *p)
     if (p->nx > (int64_t(1) << 30) || p->ny > 65535 || p->nz > 65535)
         return fail(LBM_EUNSUPPORTED, "grid extents limited to nx <= 2^30, ny, nz <= 65535");
     const double cells = double(p->nx) * double(p->ny) * double(p->nz);
-    if (cells * lattice_q(p->lattice) * storage_bytes(p->storage) > 4.0e12)
-        return fail(LBM_EUNSUPPORTED, "grid too large");
+    if (cells * double(storage_bytes(p->storage)) >= 4294967296.0)
+        return fail(LBM_EUNSUPPORTED,
+                    "one population plane (nx*ny*nz values) must stay below 4 GiB");
     if (!std::isfinite(p->tau_hat) || !(p->tau_hat > 0.5))
         return fail(LBM_EINVAL, "tau_hat must be finite and > 0.5 (got %g)", p->tau_hat);
     if (p->eq_order < 0 || p->eq_order == 1)

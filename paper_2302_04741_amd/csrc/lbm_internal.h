@@ -36,6 +36,67 @@ __host__ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
+// fused multiply-add in the precision of its arguments
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// buffer access to one population plane: scalar resource (plane base, size),
+// scalar row offset, per-lane 32-bit x offset.  Addressing costs no VALU
+// work, and the hardware range check drops accesses past the plane.
+// ---------------------------------------------------------------------------
+constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer, 32-bit data format
+// Cache policy of the step's population traffic: non-temporal (every element is
+// read once and written once per step; measured ~4% faster than the default).
+constexpr int BUF_NT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes),
+                                             BUF_DWORD3);
+}
+
+template <class S> struct BufIO;
+template <> struct BufIO<float> {
+    __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
+    {
+        return __builtin_bit_cast(float,
+                                  __builtin_amdgcn_raw_buffer_load_b32(r, int(v), int(s), BUF_NT));
+    }
+    __device__ static __forceinline__ void store(float x, __amdgpu_buffer_rsrc_t r, uint32_t v,
+                                                 uint32_t s)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, int(v), int(s),
+                                              BUF_NT);
+    }
+};
+template <> struct BufIO<double> {
+    __device__ static __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
+    {
+        return __builtin_bit_cast(double,
+                                  __builtin_amdgcn_raw_buffer_load_b64(r, int(v), int(s), BUF_NT));
+    }
+    __device__ static __forceinline__ void store(double x, __amdgpu_buffer_rsrc_t r, uint32_t v,
+                                                 uint32_t s)
+    {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, int(v), int(s), BUF_NT);
+    }
+};
+template <> struct BufIO<__half> {
+    __device__ static __forceinline__ __half load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
+    {
+        return __builtin_bit_cast(__half,
+                                  __builtin_amdgcn_raw_buffer_load_b16(r, int(v), int(s), BUF_NT));
+    }
+    __device__ static __forceinline__ void store(__half x, __amdgpu_buffer_rsrc_t r, uint32_t v,
+                                                 uint32_t s)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, int(v),
+                                              int(s), BUF_NT);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // lattice traits (velocity order: rest, then +c/-c pairs shell by shell)
 // ---------------------------------------------------------------------------

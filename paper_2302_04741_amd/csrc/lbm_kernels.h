@@ -59,20 +59,25 @@ template <class L, class S, class T>
 __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &gd, int x, int y,
                                        int z, T (&h)[L::Q])
 {
-    int xs[7], ys[7], zs[7];
+    // x offsets are per lane (7 distinct byte offsets); y and z are uniform over
+    // the block, so each row offset and each plane resource is a scalar.
+    uint32_t xs[7];
+    int ys[7], zs[7];
 #pragma unroll
     for (int d = 0; d < 7; ++d) {
-        xs[d] = wrap3(x - (d - 3), gd.nx);
+        xs[d] = uint32_t(wrap3(x - (d - 3), gd.nx)) * uint32_t(sizeof(S));
         ys[d] = wrap3(y - (d - 3), gd.ny);
         zs[d] = (L::D == 3) ? wrap3(z - (d - 3), gd.nz) : 0;
     }
     const int64_t N = gd.N;
+    const uint32_t plane_bytes = uint32_t(N * int64_t(sizeof(S)));
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
-        const int64_t row = (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx;
-        const S *plane = A + int64_t(i) * N + row;
-        h[i] = Codec<L, S>::template load<i, T>(plane[xs[cx + 3]]);
+        const uint32_t row =
+            uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx) * uint32_t(sizeof(S));
+        const auto r = plane_rsrc(A + int64_t(i) * N, plane_bytes);
+        h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
     });
 }
 
@@ -98,7 +103,10 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= gd.nx) return;
     const int64_t N = gd.N;
-    const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
+    const int64_t rowbase = (int64_t(z) * gd.ny + y) * gd.nx;  // uniform
+    const int64_t cell = rowbase + x;
+    // one population plane is < 4 GiB (checked at creation), so 32-bit byte
+    // offsets address it
 
     T h[L::Q];
     gather<L, S, T>(A, gd, x, y, z, h);
@@ -115,18 +123,20 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
     // every term is a small deviation, so the rounding stays at the size of h.
     const T om = T(co.om);
     const T drho = cs.drho;
-    S *__restrict__ out = B + cell;
+    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
+    const uint32_t ro = uint32_t(rowbase) * uint32_t(sizeof(S));
+    const uint32_t plane_bytes = uint32_t(N * int64_t(sizeof(S)));
     combo_pairs<L, T, EQ, FO, true>(cs, om, T(co.cf), [&](auto IP, auto IM, T ev, T od) {
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip));
-        const T dp = __builtin_fma(T(w), drho, -h[ip]);
-        out[int64_t(ip) * N] =
-            Codec<L, S>::template store<ip, T>(h[ip] + __builtin_fma(om, dp, ev + od));
+        const T dp = fma_t(T(w), drho, -h[ip]);
+        BufIO<S>::store(Codec<L, S>::template store<ip, T>(h[ip] + fma_t(om, dp, ev + od)),
+                        plane_rsrc(B + int64_t(ip) * N, plane_bytes), xo, ro);
         if constexpr (im >= 0) {
-            const T dm = __builtin_fma(T(w), drho, -h[im]);
-            out[int64_t(im) * N] =
-                Codec<L, S>::template store<im, T>(h[im] + __builtin_fma(om, dm, ev - od));
+            const T dm = fma_t(T(w), drho, -h[im]);
+            BufIO<S>::store(Codec<L, S>::template store<im, T>(h[im] + fma_t(om, dm, ev - od)),
+                            plane_rsrc(B + int64_t(im) * N, plane_bytes), xo, ro);
         }
     });
 }
