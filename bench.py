@@ -69,6 +69,74 @@ def measured_traffic():
         return None
 
 
+def _pmc_per_kernel(csv_path, counter):
+    import csv
+    import collections
+
+    vals = collections.defaultdict(list)
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                vals[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return vals
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
+    """Turn two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+    into HBM bytes per step launch.  Each counter is scaled by what it reads for
+    the plain 2 GiB device copy (--copy-calib) of the same run: a copy moves
+    exactly 2 GiB in each direction."""
+    fetch = _pmc_per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _pmc_per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = float(1 << 31)
+
+    def pick(vals, needle, big=True):
+        keys = [k for k in vals if needle in k[0]]
+        if big:
+            keys = [max(keys, key=lambda k: k[1])]
+        v = [x for k in keys for x in vals[k]]
+        return sum(v) / len(v), len(v)
+
+    f_copy, _ = pick(fetch, "copyBuffer")
+    w_copy, _ = pick(write, "copyBuffer")
+    f_step, nf = pick(fetch, "step_kernel")
+    w_step, nw = pick(write, "step_kernel")
+    f_scale = copy_bytes / (f_copy * 1024.0)
+    w_scale = copy_bytes / (w_copy * 1024.0)
+    read_b = f_step * 1024.0 * f_scale
+    write_b = w_step * 1024.0 * w_scale
+    alg = 2 * 39 * 4 * 256 ** 3
+    out = {
+        "kernel_source_hash": kernel_source_hash(),
+        "fetch_kib_per_launch_raw": round(f_step, 1),
+        "write_kib_per_launch_raw": round(w_step, 1),
+        "fetch_scale_from_copy": round(f_scale, 4),
+        "write_scale_from_copy": round(w_scale, 4),
+        "hbm_read_bytes_per_launch": round(read_b),
+        "hbm_write_bytes_per_launch": round(write_b),
+        "hbm_bytes_per_launch": round(read_b + write_b),
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": round((read_b + write_b) / alg, 4),
+        "read_over_algorithmic": round(read_b / (alg / 2), 4),
+        "write_over_algorithmic": round(write_b / (alg / 2), 4),
+        "dispatches_averaged": "%d fetch, %d write" % (nf, nw),
+    }
+    with open(out_path, "w") as fh:
+        fh.write("# HBM traffic of the fused step kernel, D3Q39 FP32 (deviation storage), 256^3 Kolmogorov\n")
+        fh.write("# counter runs (repo root, MI355X), one counter per run:\n")
+        fh.write("#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python3 bench.py "
+                 "--steps 5 --warmup 2 --cpu-steps 0 --copy-calib\n")
+        fh.write("#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python3 bench.py "
+                 "--steps 5 --warmup 2 --cpu-steps 0 --copy-calib\n")
+        fh.write("# summarised by:\n#   python3 bench.py --summarize-pmc "
+                 "gpurun_out/pmc_fetch/pmc_counter_collection.csv "
+                 "gpurun_out/pmc_write/pmc_counter_collection.csv\n")
+        fh.write("# scale = 2 GiB / counter value of the 2 GiB plain device copy in the same run\n")
+        for k, v in out.items():
+            fh.write("%s: %s\n" % (k, v))
+    return out
+
+
 def cpu_baseline(wl, steps: int):
     import oracle
 
@@ -92,11 +160,18 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=256, help="grid side (default 256)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--cpu-steps", type=int, default=6,
                     help="oracle steps of the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter summary under profiles/ and exit (no GPU)")
     args = ap.parse_args(argv)
+
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
+                                       PMC_SUMMARY)))
+        return 0
 
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path is the single-GPU fused step "
