@@ -158,7 +158,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (default 256)")
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="oracle steps of the CPU baseline (0 = skip)")
@@ -218,7 +218,7 @@ def main(argv=None) -> int:
 
     N = wl.ncell
     Q = 39
-    sbytes = 4 if args.storage == "f32" else 8
+    sbytes = {"f32": 4, "f64": 8, "f16dev": 2}[args.storage]
     ms_per_step = ms_events / args.steps
     mlups = N / (ms_per_step * 1e-3) / 1e6
     bytes_per_launch = 2.0 * Q * sbytes * N
@@ -236,7 +236,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "f32" else "f64",
+        "dtype": {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}[args.storage],
         "data": "synthetic",
         "config": {
             "workload": "D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=0.8, "

@@ -110,8 +110,6 @@ lbm_status check_params(const lbm_params *p)
         return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
     if (p->storage != LBM_F64 && p->storage != LBM_F32 && p->storage != LBM_F16DEV)
         return fail(LBM_EINVAL, "unknown storage %d", p->storage);
-    if (p->storage == LBM_F16DEV)
-        return fail(LBM_EUNSUPPORTED, "LBM_F16DEV storage is not available in this build");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_EINVAL, "grid extents must be >= 1 (got %lld x %lld x %lld)",
                     (long long)p->nx, (long long)p->ny, (long long)p->nz);

@@ -21,6 +21,8 @@ hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void
     if (lat == 0 && storage == 1) return launch_step_ls<0, float>(eq, fo, A, B, gd, fd, co, lc);
     if (lat == 1 && storage == 0) return launch_step_ls<1, double>(eq, fo, A, B, gd, fd, co, lc);
     if (lat == 1 && storage == 1) return launch_step_ls<1, float>(eq, fo, A, B, gd, fd, co, lc);
+    if (lat == 0 && storage == 2) return launch_step_ls<0, __half>(eq, fo, A, B, gd, fd, co, lc);
+    if (lat == 1 && storage == 2) return launch_step_ls<1, __half>(eq, fo, A, B, gd, fd, co, lc);
     return hipErrorInvalidValue;
 }
 

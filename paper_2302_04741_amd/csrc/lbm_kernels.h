@@ -44,11 +44,13 @@ template <class L> struct Codec<L, __half> {
     }
     template <int I, class T> __device__ static __forceinline__ T load(__half v)
     {
-        return T(__half2float(v)) * T(1.0 / scale<I>());
+        constexpr double inv = 1.0 / scale<I>();  // exact: a power of two
+        return T(__half2float(v)) * T(inv);
     }
     template <int I, class T> __device__ static __forceinline__ __half store(T h)
     {
-        return __float2half_rn(float(h * T(scale<I>())));
+        constexpr double sc = scale<I>();
+        return __float2half_rn(float(h * T(sc)));
     }
 };
 

@@ -95,6 +95,19 @@ def test_parity_fp32_storage_short(sim_mod, oracle_mod, lat, dims):
     check_parity(sim_mod, oracle_mod, wl, 25, tol=TOL32_SHORT, storage="f32")
 
 
+# F16 deviations: binary16 keeps 11 significant bits of each stored deviation
+# (relative 4.9e-4 of a deviation of up to ~25% of w_i), so a step perturbs
+# rho and theta by ~1e-5 and the bars over 25 steps are 2e-4 (rho, theta) and
+# 2e-3 (u).
+TOL16_SHORT = (2e-4, 2e-3, 2e-4)
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q37", (70, 9, 1)), ("D3Q39", (9, 7, 66))])
+def test_parity_f16dev_storage_short(sim_mod, oracle_mod, lat, dims):
+    wl = workloads.random_smooth(lat, dims, seed=13, force_kind="axis", g_amp=1e-3)
+    check_parity(sim_mod, oracle_mod, wl, 25, tol=TOL16_SHORT, storage="f16dev")
+
+
 def test_initial_moments_are_the_inputs(sim_mod):
     wl = workloads.random_smooth("D2Q37", (20, 13, 1), seed=1, force_kind="uniform")
     s = sim_mod.from_workload(wl)
