@@ -185,6 +185,52 @@ LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
  * 512 or 1024).  0 restores the default.  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
+/* ---- batching: several simulations per launch, and captured step loops ---- */
+
+typedef struct lbm_batch lbm_batch; /* opaque host handle */
+typedef struct lbm_graph lbm_graph; /* opaque host handle */
+
+/* Device workspace of a batch of up to max_sims simulations (its tile table). */
+LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
+
+/* A batch advances its member simulations together: every step is ONE launch
+ * of a persistent multi-grid kernel whose blocks walk a list of tiles (one
+ * tile = one grid row of one member) with a fixed stride.  Members must share
+ * lattice, storage, eq_order and force_order; grid sizes, tau_hat, rho0 and
+ * forces may differ.  The per-cell arithmetic is that of lbm_step, so a
+ * member's result does not depend on the other members.  Runs on hip_stream. */
+LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
+                                    void *hip_stream, lbm_batch **out);
+
+/* Set the members (1..max_sims handles, no duplicates) and upload the tile
+ * table on the batch's stream.  Call again after a member was stepped or had
+ * its force changed outside the batch (lbm_batch_step refuses stale tables).
+ * Destroying a member leaves the batch unusable until the next lbm_batch_set. */
+LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count);
+
+/* Advance every member by nsteps (>= 0) steps, one launch per step. */
+LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Persistent grid of the multi-grid kernel: blocks of 256 threads (0 = default). */
+LBM_API lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
+
+/* NULL-safe; does not free the workspace and does not wait for queued work. */
+LBM_API void lbm_batch_destroy(lbm_batch *b);
+
+/* Capture nsteps (even, > 0) steps of one simulation (s) or one batch (b) --
+ * exactly one of them non-NULL -- into a HIP graph on its stream, which must
+ * not be the null stream.  Capturing executes nothing and leaves the state
+ * unchanged.  The graph holds the buffers of the handle: it stays valid while
+ * the handle lives and is not re-initialised (lbm_set_force before the first
+ * step rebuilds in place, so it is fine; a new lbm_batch_set is not). */
+LBM_API lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph **out);
+
+/* Replay the captured steps `repeats` times (asynchronous on the stream). */
+LBM_API lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats);
+
+/* NULL-safe. */
+LBM_API void lbm_graph_destroy(lbm_graph *g);
+
 /* The velocity set compiled into the library (host call, no GPU needed):
  * c: Q*3 ints, w: Q doubles, r: the scale with xi_i = r c_i.  Returns Q, or a
  * negative lbm_status. */

@@ -1,0 +1,146 @@
+"""Autotuner of launch shapes.
+
+* Single-grid step: threads per block (64 ... 1024) per (lattice, storage,
+  equilibrium order, force order, grid class).
+* Multi-grid (batched) step: number of persistent blocks per (lattice, storage,
+  orders, batch class).
+
+Candidates are timed with HIP events on scratch simulations of the same shape
+(smooth synthetic fields; the cost of a step does not depend on the data), so
+tuning never touches a caller's state.  Results are cached in a JSON file
+(``$LBM_AUTOTUNE_CACHE``, default ``~/.cache/paper_2302_04741_amd/autotune.json``).
+Every launch shape gives bitwise the same results, so tuning only affects speed.
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+
+BLOCK_CANDIDATES = (64, 128, 256, 512, 1024)
+BATCH_CANDIDATES = (512, 1024, 2048, 4096, 8192)
+
+_lock = threading.Lock()
+
+
+def cache_path() -> str:
+    return os.path.expanduser(os.environ.get(
+        "LBM_AUTOTUNE_CACHE", "~/.cache/paper_2302_04741_amd/autotune.json"))
+
+
+def _bucket(n: int) -> int:
+    b = 1
+    while b < n:
+        b *= 2
+    return b
+
+
+def grid_class(dims) -> str:
+    nx, ny, nz = (tuple(int(d) for d in dims) + (1, 1))[:3]
+    return "x%d_r%d" % (_bucket(nx), _bucket(ny * nz))
+
+
+def batch_class(dims_list) -> str:
+    cells = sum(int(d[0]) * int(d[1]) * (int(d[2]) if len(d) > 2 else 1) for d in dims_list)
+    return "n%d_c%d" % (_bucket(len(dims_list)), _bucket(cells))
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key: str, value) -> None:
+    with _lock:
+        data = _load_cache()
+        data[key] = value
+        path = cache_path()
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+
+
+def _time_steps(torch, step, stream, steps: int) -> float:
+    step(2)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _scratch(lattice, dims, storage, eq_order, force_order, seed=0):
+    from . import sim, workloads
+
+    wl = workloads.random_smooth(lattice, tuple(dims), seed=seed, force_kind="uniform",
+                                 force_order=force_order)
+    wl.eq_order = eq_order
+    return sim.from_workload(wl, storage=storage)
+
+
+def block_key(lattice, storage, eq_order, force_order, dims) -> str:
+    return "block/%s/%s/eq%d/fo%d/%s" % (lattice, storage, eq_order, force_order, grid_class(dims))
+
+
+def tune_block(lattice: str, dims, storage: str = "f32", eq_order: int = 0, force_order: int = 4,
+               steps: int = 10, retune: bool = False) -> int:
+    """Fastest threads-per-block for this class of grid (cached)."""
+    key = block_key(lattice, storage, eq_order, force_order, dims)
+    if not retune:
+        hit = _load_cache().get(key)
+        if hit:
+            return int(hit["block"])
+    import torch
+
+    s = _scratch(lattice, dims, storage, eq_order, force_order)
+    times = {}
+    for b in BLOCK_CANDIDATES:
+        if storage == "f64" and b > 256:
+            continue  # FP64 blocks are capped at 256 threads
+        s.set_block(b)
+        times[b] = _time_steps(torch, s.step, s.stream, steps)
+    s.close()
+    best = min(times, key=times.get)
+    _store(key, {"block": best, "ms_per_step": times})
+    return best
+
+
+def batch_key(lattice, storage, eq_order, force_order, dims_list) -> str:
+    return "batch/%s/%s/eq%d/fo%d/%s" % (lattice, storage, eq_order, force_order,
+                                         batch_class(dims_list))
+
+
+def tune_batch_blocks(lattice: str, dims_list, storage: str = "f32", eq_order: int = 0,
+                      force_order: int = 4, steps: int = 10, retune: bool = False) -> int:
+    """Fastest persistent grid of the multi-grid kernel for this class of batch."""
+    key = batch_key(lattice, storage, eq_order, force_order, dims_list)
+    if not retune:
+        hit = _load_cache().get(key)
+        if hit:
+            return int(hit["blocks"])
+    import torch
+
+    from . import sim
+
+    sims = [_scratch(lattice, d, storage, eq_order, force_order, seed=k)
+            for k, d in enumerate(dims_list)]
+    b = sim.Batch(len(sims))
+    b.set(sims)
+    times = {}
+    for nb in BATCH_CANDIDATES:
+        b.set_blocks(nb)
+        times[nb] = _time_steps(torch, b.step, b.stream, steps)
+    b.close()
+    for s in sims:
+        s.close()
+    best = min(times, key=times.get)
+    _store(key, {"blocks": best, "ms_per_step": times})
+    return best

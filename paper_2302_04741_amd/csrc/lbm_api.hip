@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbm.h"
 #include "lbm_internal.h"
@@ -34,6 +35,7 @@ struct lbm_sim {
     double *totals_dev;
     int64_t step;
     int block;
+    int64_t gen;  // bumped when launch arguments change (force, block, stream)
 };
 
 namespace {
@@ -253,6 +255,7 @@ lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis
         if (e != hipSuccess) return dev_fail(e, "force table conversion");
     }
     s->fd = nf;
+    s->gen++;
     if (s->step == 0) {
         e = launch_init(s->p.lattice, s->p.storage, s->eq, s->p.force_order, mrho, mu, mth,
                         s->pop[s->cur], s->gd, s->fd, s->co, cfg(s));
@@ -356,6 +359,7 @@ lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     s->stream = static_cast<hipStream_t>(hip_stream);
+    s->gen++;
     return ok();
 }
 
@@ -366,6 +370,7 @@ lbm_status lbm_set_block(lbm_sim *s, int32_t threads)
         threads != 1024)
         return fail(LBM_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024 (got %d)", threads);
     s->block = threads;
+    s->gen++;
     return ok();
 }
 
@@ -384,6 +389,275 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.1.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.2.0"; }
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct lbm_batch {
+    int32_t max_sims;
+    hipStream_t stream;
+    TileSim *table;  // device, in the caller's workspace
+    std::vector<lbm_sim *> sims;
+    std::vector<int64_t> step_at_set;  // members' step counts when the table was built
+    std::vector<int64_t> gen_at_set;   // members' launch-argument generations then
+    int64_t generation;                // bumped by every lbm_batch_set
+    int64_t steps_done;                // batch steps since the table was built
+    int64_t ntiles;
+    int blocks;
+};
+
+struct lbm_graph {
+    lbm_sim *s;
+    lbm_batch *b;
+    int64_t nsteps;
+    int64_t gen;     // launch-argument generation of s, or batch generation of b
+    int32_t cur0;    // s: buffer holding the state at capture
+    int32_t parity0; // b: parity of the batch step count at capture
+    hipStream_t stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+constexpr int BATCH_DEFAULT_BLOCKS = 2048;
+
+lbm_status batch_check(const lbm_batch *b)
+{
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        if (b->sims[k]->step != b->step_at_set[k] + b->steps_done)
+            return fail(LBM_EINVAL,
+                        "member %zu was stepped outside the batch; call lbm_batch_set again", k);
+        if (b->sims[k]->gen != b->gen_at_set[k])
+            return fail(LBM_EINVAL,
+                        "member %zu changed force, block or stream; call lbm_batch_set again", k);
+    }
+    return LBM_OK;
+}
+
+lbm_status batch_launch(lbm_batch *b, int64_t nsteps)
+{
+    const lbm_sim *s0 = b->sims[0];
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int parity = int((b->steps_done + k) & 1);
+        hipError_t e = launch_multi_step(s0->p.lattice, s0->p.storage, s0->eq, s0->p.force_order,
+                                         b->table, int(b->sims.size()), b->ntiles, parity,
+                                         b->blocks, b->stream);
+        if (e != hipSuccess) return dev_fail(e, "multi-grid step launch");
+    }
+    return LBM_OK;
+}
+
+void batch_advance(lbm_batch *b, int64_t nsteps)
+{
+    b->steps_done += nsteps;
+    for (lbm_sim *s : b->sims) {
+        s->cur ^= int(nsteps & 1);
+        s->step += nsteps;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(int32_t max_sims)
+{
+    if (max_sims < 1 || max_sims > (1 << 20)) return 0;
+    return align_up(size_t(max_sims) * sizeof(TileSim));
+}
+
+lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
+                            void *hip_stream, lbm_batch **out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_sims < 1 || max_sims > (1 << 20))
+        return fail(LBM_EINVAL, "max_sims must be in [1, 2^20] (got %d)", max_sims);
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN)
+        return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < lbm_batch_workspace_bytes(max_sims))
+        return fail(LBM_ENOSPACE, "batch workspace has %zu bytes, %zu needed", workspace_bytes,
+                    lbm_batch_workspace_bytes(max_sims));
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_EINVAL, "out of host memory");
+    b->max_sims = max_sims;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->table = static_cast<TileSim *>(workspace);
+    b->steps_done = 0;
+    b->ntiles = 0;
+    b->generation = 0;
+    b->blocks = BATCH_DEFAULT_BLOCKS;
+    *out = b;
+    return ok();
+}
+
+lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (!sims) return fail(LBM_EINVAL, "sims is NULL");
+    if (count < 1 || count > b->max_sims)
+        return fail(LBM_EINVAL, "count must be in [1, %d] (got %d)", b->max_sims, count);
+    std::vector<TileSim> host(static_cast<size_t>(count));
+    int64_t tiles = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const lbm_sim *s = sims[k];
+        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
+        const lbm_sim *s0 = sims[0];
+        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
+            s->p.force_order != s0->p.force_order)
+            return fail(LBM_EINVAL,
+                        "batch members must share lattice, storage, eq_order and force_order");
+        TileSim &t = host[size_t(k)];
+        t.pop[0] = s->pop[0];
+        t.pop[1] = s->pop[1];
+        t.cur = s->cur;
+        t.pad = 0;
+        t.tile_begin = tiles;
+        t.gd = s->gd;
+        t.fd = s->fd;
+        t.co = s->co;
+        tiles += int64_t(s->p.ny) * s->p.nz;
+    }
+    hipError_t e = hipMemcpyAsync(b->table, host.data(), host.size() * sizeof(TileSim),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return dev_fail(e, "tile table upload");
+    b->sims.assign(sims, sims + count);
+    b->step_at_set.clear();
+    b->gen_at_set.clear();
+    for (lbm_sim *s : b->sims) {
+        b->step_at_set.push_back(s->step);
+        b->gen_at_set.push_back(s->gen);
+    }
+    b->steps_done = 0;
+    b->generation++;
+    b->ntiles = tiles;
+    return ok();
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (b->sims.empty()) return fail(LBM_EINVAL, "batch has no members (call lbm_batch_set)");
+    lbm_status st = batch_check(b);
+    if (st != LBM_OK) return st;
+    st = batch_launch(b, nsteps);
+    if (st != LBM_OK) return st;
+    batch_advance(b, nsteps);
+    return ok();
+}
+
+lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (blocks < 0 || blocks > (1 << 22)) return fail(LBM_EINVAL, "blocks out of range");
+    b->blocks = blocks ? blocks : BATCH_DEFAULT_BLOCKS;
+    return ok();
+}
+
+void lbm_batch_destroy(lbm_batch *b) { delete b; }
+
+// ---------------------------------------------------------------------------
+// captured step loops
+// ---------------------------------------------------------------------------
+lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph **out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if ((s == nullptr) == (b == nullptr))
+        return fail(LBM_EINVAL, "give exactly one of a simulation and a batch");
+    if (nsteps <= 0 || (nsteps & 1))
+        return fail(LBM_EINVAL, "nsteps must be even and > 0 (got %lld)", (long long)nsteps);
+    if (b && b->sims.empty()) return fail(LBM_EINVAL, "batch has no members");
+    if (b) {
+        lbm_status stc = batch_check(b);
+        if (stc != LBM_OK) return stc;
+    }
+    hipStream_t stream = s ? s->stream : b->stream;
+    if (!stream) return fail(LBM_EINVAL, "graph capture needs a non-null stream");
+    lbm_graph *g = new (std::nothrow) lbm_graph();
+    if (!g) return fail(LBM_EINVAL, "out of host memory");
+    g->s = s;
+    g->b = b;
+    g->nsteps = nsteps;
+    g->stream = stream;
+    g->gen = s ? s->gen : b->generation;
+    g->cur0 = s ? s->cur : 0;
+    g->parity0 = b ? int32_t(b->steps_done & 1) : 0;
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return dev_fail(e, "begin capture");
+    }
+    lbm_status st = LBM_OK;
+    if (s) {
+        const int cur0 = s->cur;
+        for (int64_t k = 0; k < nsteps && st == LBM_OK; ++k) {
+            hipError_t el = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
+                                        s->pop[s->cur], s->pop[s->cur ^ 1], s->gd, s->fd, s->co,
+                                        cfg(s));
+            if (el != hipSuccess) st = dev_fail(el, "step launch during capture");
+            s->cur ^= 1;
+        }
+        s->cur = cur0;  // nothing ran: restore
+    } else {
+        st = batch_launch(b, nsteps);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(stream, &graph);
+    if (st != LBM_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return st != LBM_OK ? st : dev_fail(e, "end capture");
+    }
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return dev_fail(e, "graph instantiate");
+    }
+    g->graph = graph;
+    *out = g;
+    return ok();
+}
+
+lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats)
+{
+    if (!g) return fail(LBM_EINVAL, "graph is NULL");
+    if (repeats < 0) return fail(LBM_EINVAL, "repeats must be >= 0");
+    if (g->s && (g->s->gen != g->gen || g->s->cur != g->cur0))
+        return fail(LBM_EINVAL,
+                    "the simulation changed since capture (force, block, stream or buffer parity)");
+    if (g->b) {
+        if (g->b->generation != g->gen || int32_t(g->b->steps_done & 1) != g->parity0)
+            return fail(LBM_EINVAL, "the batch changed since capture (members or step parity)");
+        lbm_status stc = batch_check(g->b);
+        if (stc != LBM_OK) return stc;
+    }
+    for (int64_t r = 0; r < repeats; ++r) {
+        hipError_t e = hipGraphLaunch(g->exec, g->stream);
+        if (e != hipSuccess) return dev_fail(e, "graph launch");
+    }
+    const int64_t n = g->nsteps * repeats;  // even: buffers end where they started
+    if (g->s) {
+        g->s->step += n;
+    } else {
+        batch_advance(g->b, n);
+    }
+    return ok();
+}
+
+void lbm_graph_destroy(lbm_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
 
 }  // extern "C"

@@ -26,6 +26,21 @@ hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const TileSim *table, int nsims,
+                             int64_t ntiles, int parity, int blocks, hipStream_t stream)
+{
+#define LBM_MS(L, S) \
+    return launch_multi_step_ls<L, S>(eq, fo, table, nsims, ntiles, parity, blocks, stream)
+    if (lat == 0 && storage == 0) LBM_MS(0, double);
+    if (lat == 0 && storage == 1) LBM_MS(0, float);
+    if (lat == 0 && storage == 2) LBM_MS(0, __half);
+    if (lat == 1 && storage == 0) LBM_MS(1, double);
+    if (lat == 1 && storage == 1) LBM_MS(1, float);
+    if (lat == 1 && storage == 2) LBM_MS(1, __half);
+#undef LBM_MS
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_init(int lat, int storage, int eq, int fo, const double *rho, const double *u,
                        const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
                        const StepCoef &co, const LaunchCfg &lc)

@@ -166,7 +166,18 @@ struct ForceDesc {
 struct StepCoef {
     double om;   // 1/tau^
     double cf;   // 1 - 1/(2 tau^)
-    double rho0; // reference density of F16 deviations
+    double rho0; // reference density of the stored deviations
+};
+
+// One member of a multi-grid batch (device table entry).
+struct TileSim {
+    const void *pop[2];  // the two population buffers
+    int32_t cur;         // buffer holding the state when the table was built
+    int32_t pad;
+    int64_t tile_begin;  // first tile (grid row) of this simulation in the list
+    GridDims gd;
+    ForceDesc fd;
+    StepCoef co;
 };
 
 // Periodic wrap of v in [-3, n + 3) into [0, n), valid for any n >= 1.
@@ -491,12 +502,17 @@ hipError_t launch_totals(int lat, int storage, const void *A, double *partials, 
                          const GridDims &gd, const StepCoef &co, hipStream_t stream);
 hipError_t launch_convert(int storage, const double *src, void *dst, int64_t n,
                           hipStream_t stream);
+hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const TileSim *table, int nsims,
+                             int64_t ntiles, int parity, int blocks, hipStream_t stream);
 
 // Per-lattice / per-storage pieces, each explicitly instantiated in its own
 // translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
 template <int LAT, class S>
 hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                           const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_multi_step_ls(int eq, int fo, const TileSim *table, int nsims, int64_t ntiles,
+                                int parity, int blocks, hipStream_t stream);
 template <int LAT>
 hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
                          const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,

@@ -93,17 +93,15 @@ template <class S> constexpr int step_max_threads()
     return sizeof(typename ArithOf<S>::type) == 8 ? 256 : 1024;
 }
 
+// The fused update of one cell (x, y, z): gather, moments, equilibrium, stress,
+// force, relaxation, store.  y and z must be uniform over the wavefront.
 template <int LAT, class S, int EQ, int FO>
-__global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__restrict__ A,
-                                                                     S *__restrict__ B,
-                                                                     GridDims gd, ForceDesc fd,
-                                                                     StepCoef co)
+__device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict__ B,
+                                          const GridDims &gd, const ForceDesc &fd,
+                                          const StepCoef &co, int x, int y, int z)
 {
     using L = Lattice<LAT>;
     using T = typename ArithOf<S>::type;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
-    if (x >= gd.nx) return;
     const int64_t N = gd.N;
     const int64_t rowbase = (int64_t(z) * gd.ny + y) * gd.nx;  // uniform
     const int64_t cell = rowbase + x;
@@ -141,6 +139,51 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
                             plane_rsrc(B + int64_t(im) * N, plane_bytes), xo, ro);
         }
     });
+}
+
+template <int LAT, class S, int EQ, int FO>
+__global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__restrict__ A,
+                                                                     S *__restrict__ B,
+                                                                     GridDims gd, ForceDesc fd,
+                                                                     StepCoef co)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= gd.nx) return;
+    step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// K1b: persistent multi-grid step.  Several simulations (same lattice, storage
+// and orders; any grid sizes, relaxation times and forces) advance one step in
+// one launch.  The work is a list of tiles -- one tile is one grid row (all x)
+// of one simulation -- and each block walks the list with a fixed stride, so
+// every block exits after at most ceil(ntiles / gridDim.x) tiles and the
+// tile -> block assignment (hence every result) does not depend on timing.
+// ---------------------------------------------------------------------------
+template <int LAT, class S, int EQ, int FO>
+__global__ void __launch_bounds__(256) multi_step_kernel(const TileSim *__restrict__ sims,
+                                                          int nsims, int64_t ntiles, int parity)
+{
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        // the simulation owning tile t: last s with tile_begin <= t (uniform)
+        int lo = 0, hi = nsims - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sims[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const TileSim &sd = sims[lo];
+        const uint32_t row = uint32_t(t - sd.tile_begin);  // ny * nz < 2^32
+        const int y = int(row % uint32_t(sd.gd.ny)), z = int(row / uint32_t(sd.gd.ny));
+        const int c = sd.cur ^ parity;
+        const S *A = static_cast<const S *>(sd.pop[c]);
+        S *B = static_cast<S *>(const_cast<void *>(sd.pop[c ^ 1]));
+        for (int x0 = 0; x0 < sd.gd.nx; x0 += int(blockDim.x)) {
+            const int x = x0 + int(threadIdx.x);
+            if (x < sd.gd.nx) step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -45,6 +45,18 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
     });
 }
 
+template <int LAT, class S>
+hipError_t launch_multi_step_ls(int eq, int fo, const TileSim *table, int nsims, int64_t ntiles,
+                                int parity, int blocks, hipStream_t stream)
+{
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        hipLaunchKernelGGL((multi_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
+                           dim3(unsigned(blocks)), dim3(256), 0, stream, table, nsims, ntiles,
+                           parity);
+        return hipGetLastError();
+    });
+}
+
 template <int LAT>
 hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
                          const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,

@@ -1,0 +1,7 @@
+// Multi-grid (batched) step kernels for D2Q37 storage f16 (all equilibrium and force orders).
+#include "lbm_launch.h"
+
+namespace lbm {
+template hipError_t launch_multi_step_ls<0, __half>(int, int, const TileSim *, int, int64_t, int,
+                                                     int, hipStream_t);
+}  // namespace lbm

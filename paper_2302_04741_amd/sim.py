@@ -208,3 +208,83 @@ def from_workload(wl, storage="f64", **kw) -> Sim:
             eq_order=wl.eq_order, force_order=wl.force_order, force_field=force_field, **kw)
     s.set_workload_force(wl.force)
     return s
+
+
+class Graph:
+    """A captured loop of `nsteps` (even) steps of a Sim or a Batch (HIP graph)."""
+
+    def __init__(self, target, nsteps: int):
+        L = load()
+        h = ctypes.c_void_p()
+        if isinstance(target, Sim):
+            check(L.lbm_graph_create(target.handle, None, int(nsteps), ctypes.byref(h)))
+        else:
+            check(L.lbm_graph_create(None, target.handle, int(nsteps), ctypes.byref(h)))
+        self._h = h
+        self.nsteps = int(nsteps)
+        self.target = target
+
+    def launch(self, repeats: int = 1):
+        check(load().lbm_graph_launch(self._h, int(repeats)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lbm_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several Sims advanced together by the persistent multi-grid kernel: one
+    launch per step for all members (same lattice, storage and orders; any grid
+    sizes, relaxation times and forces)."""
+
+    def __init__(self, max_sims: int, device=None, stream=None):
+        torch = _torch()
+        L = load()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = L.lbm_batch_workspace_bytes(int(max_sims))
+        if nbytes == 0:
+            raise ValueError("max_sims out of range")
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._raw = raw
+        ws = raw.data_ptr() + (-raw.data_ptr()) % 256
+        h = ctypes.c_void_p()
+        check(L.lbm_batch_create(int(max_sims), ctypes.c_void_p(ws), ctypes.c_size_t(nbytes),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.members = []
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("batch is closed")
+        return self._h
+
+    def set(self, sims):
+        arr = (ctypes.c_void_p * len(sims))(*[s.handle.value for s in sims])
+        check(load().lbm_batch_set(self.handle, arr, len(sims)))
+        self.members = list(sims)
+
+    def step(self, n: int = 1):
+        check(load().lbm_batch_step(self.handle, int(n)))
+
+    def set_blocks(self, blocks: int):
+        check(load().lbm_batch_set_blocks(self.handle, int(blocks)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lbm_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

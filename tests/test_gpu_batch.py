@@ -1,0 +1,161 @@
+"""Batched multi-grid stepping and captured step loops (GPU).
+
+* A batch of uneven grids (different sizes, relaxation times and forces) is
+  advanced by the persistent multi-grid kernel, one launch per step.  Each
+  member equals the same simulation run as a batch of one, bitwise: nothing is
+  reduced across cells, so a member's result cannot depend on the others.
+* Against the plain single-grid kernel the batch agrees to rounding: the same
+  cell update is inlined into two kernels and the compiler may fuse
+  multiply-adds differently (measured: <= 1 ulp of the stored value per step).
+* FP64 batch members match the CPU oracle (1e-12).
+* HIP-graph replays of a step loop equal the same number of eager steps,
+  checked after every replay with eager work and synchronisation in between.
+* Stale batches and graphs are refused.
+"""
+import numpy as np
+import pytest
+import torch
+
+from _parity import gpu_moments, oracle_run, rel_err
+from paper_2302_04741_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    from paper_2302_04741_amd import sim
+
+    return sim
+
+
+def mix(lattice, storage, seed=0):
+    rng = np.random.default_rng(seed)
+    dims_list = ([(64, 64, 1), (100, 37, 1), (256, 256, 1), (1024, 16, 1), (3, 5, 1)]
+                 if lattice == "D2Q37" else [(16, 16, 16), (40, 9, 23), (64, 64, 32), (7, 5, 3)])
+    wls = []
+    for k, dims in enumerate(dims_list):
+        kind = ["uniform", "axis", "field"][k % 3]
+        wl = workloads.random_smooth(lattice, dims, seed=seed * 100 + k, force_kind=kind,
+                                     g_amp=1e-3, tau_hat=float(rng.uniform(0.6, 1.0)))
+        wls.append(wl)
+    return wls
+
+
+@pytest.mark.parametrize("lattice,storage", [("D2Q37", "f32"), ("D3Q39", "f32"),
+                                             ("D2Q37", "f64"), ("D3Q39", "f16dev")])
+def test_batch_member_independent_of_mix_bitwise(sim_mod, lattice, storage):
+    wls = mix(lattice, storage)
+    alone = []
+    for wl in wls:
+        s = sim_mod.from_workload(wl, storage=storage)
+        b1 = sim_mod.Batch(1)
+        b1.set([s])
+        b1.step(13)
+        alone.append(s.get_populations().cpu())
+        b1.close()
+        s.close()
+    sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
+    b = sim_mod.Batch(len(sims))
+    b.set(sims)
+    b.step(6)
+    b.step(7)  # odd counts: the buffer parity is carried between calls
+    for s, ref in zip(sims, alone):
+        assert s.step_count == 13
+        assert torch.equal(s.get_populations().cpu(), ref)
+
+
+# stored-value difference allowed between the plain and the batched kernel after
+# 13 steps: a few units of the storage precision on values of size <= 1e-2
+PLAIN_VS_BATCH = {"f32": 1e-6, "f64": 1e-14, "f16dev": 1e-5}
+
+
+@pytest.mark.parametrize("lattice,storage", [("D2Q37", "f32"), ("D3Q39", "f64")])
+def test_batch_matches_plain_kernel(sim_mod, lattice, storage):
+    dt = {"f32": torch.float32, "f64": torch.float64}[storage]
+    wls = mix(lattice, storage, seed=2)
+    sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
+    b = sim_mod.Batch(len(sims))
+    b.set(sims)
+    b.step(13)
+    for wl, s in zip(wls, sims):
+        p = sim_mod.from_workload(wl, storage=storage)
+        p.step(13)
+        d = (s.get_populations().view(dt) - p.get_populations().view(dt)).abs().max().item()
+        assert d <= PLAIN_VS_BATCH[storage], (wl.dims, d)
+
+
+def test_batch_fp64_matches_oracle(sim_mod, oracle_mod):
+    wls = mix("D2Q37", "f64", seed=3)[:3]
+    sims = [sim_mod.from_workload(wl) for wl in wls]
+    b = sim_mod.Batch(4)
+    b.set(sims)
+    b.step(40)
+    for wl, s in zip(wls, sims):
+        errs = rel_err(gpu_moments(s), oracle_run(oracle_mod, wl, 40).moments())
+        assert max(errs) < 1e-12, errs
+
+
+def test_batch_rejects_stale_and_mixed_members(sim_mod):
+    from paper_2302_04741_amd._lib import LbmError
+
+    wls = mix("D2Q37", "f32")[:2]
+    a, c = (sim_mod.from_workload(wl, storage="f32") for wl in wls)
+    b = sim_mod.Batch(2)
+    b.set([a, c])
+    a.step(1)  # stepped outside the batch
+    with pytest.raises(LbmError):
+        b.step(1)
+    b.set([a, c])
+    b.step(1)
+    c.set_force([1e-4, 0.0])
+    with pytest.raises(LbmError):
+        b.step(1)
+    d = sim_mod.from_workload(wls[0], storage="f64")
+    with pytest.raises(LbmError):
+        b.set([a, d])  # different storage
+    with pytest.raises(LbmError):
+        b.set([a, a])  # duplicate
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_graph_replays_equal_eager_steps(sim_mod, storage):
+    wl = workloads.random_smooth("D3Q39", (24, 20, 18), seed=4, force_kind="axis", g_amp=1e-3)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref = sim_mod.from_workload(wl, storage=storage)
+        s = sim_mod.from_workload(wl, storage=storage)
+        g = sim_mod.Graph(s, 4)
+        for rep in range(4):
+            g.launch(1)
+            ref.step(4)
+            torch.cuda.synchronize()
+            _ = (ref.get_populations().float().sum()).item()  # eager work between replays
+            assert s.step_count == 4 * (rep + 1)
+            assert torch.equal(s.get_populations(), ref.get_populations()), rep
+        s.step(1)  # odd eager step: the graph's buffers no longer match
+        from paper_2302_04741_amd._lib import LbmError
+
+        with pytest.raises(LbmError):
+            g.launch(1)
+    torch.cuda.synchronize()
+
+
+def test_batch_graph_replays(sim_mod):
+    wls = mix("D2Q37", "f32", seed=7)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        refs = [sim_mod.from_workload(wl, storage="f32") for wl in wls]
+        bref = sim_mod.Batch(len(refs))
+        bref.set(refs)
+        sims = [sim_mod.from_workload(wl, storage="f32") for wl in wls]
+        b = sim_mod.Batch(len(sims))
+        b.set(sims)
+        g = sim_mod.Graph(b, 6)
+        for rep in range(3):
+            g.launch(1)
+            bref.step(6)  # the same kernel, launched eagerly
+            torch.cuda.synchronize()
+            for s, r in zip(sims, refs):
+                assert torch.equal(s.get_populations(), r.get_populations())
+    torch.cuda.synchronize()

@@ -188,3 +188,33 @@ def test_compiled_rule_equals_oracle_derivation(lib, oracle_mod, lattice, lat):
     assert set(mine) == set(theirs)
     for k in mine:
         assert abs(mine[k] - theirs[k]) < 1e-16 * max(1.0, 10 * theirs[k])
+
+
+def test_batch_and_graph_argument_checks(lib):
+    assert lib.lbm_batch_workspace_bytes(0) == 0
+    need = lib.lbm_batch_workspace_bytes(4)
+    assert need > 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_batch_create(4, None, need, None, ctypes.byref(h)) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_create(4, ctypes.c_void_p(0x100010), need, None,
+                                ctypes.byref(h)) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_create(4, ctypes.c_void_p(0x100000), need - 1, None,
+                                ctypes.byref(h)) == _lib.LBM_ENOSPACE
+    assert lib.lbm_batch_create(0, ctypes.c_void_p(0x100000), need, None,
+                                ctypes.byref(h)) == _lib.LBM_EINVAL
+    # a batch handle needs no GPU until members are set
+    assert lib.lbm_batch_create(4, ctypes.c_void_p(0x100000), need, None,
+                                ctypes.byref(h)) == _lib.LBM_OK
+    assert lib.lbm_batch_step(h, 1) == _lib.LBM_EINVAL  # no members
+    assert lib.lbm_batch_set(h, None, 1) == _lib.LBM_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.lbm_batch_set(h, arr, 1) == _lib.LBM_EINVAL  # NULL member
+    assert lib.lbm_batch_set(h, arr, 5) == _lib.LBM_EINVAL  # more than max_sims
+    assert lib.lbm_batch_set_blocks(h, -1) == _lib.LBM_EINVAL
+    g = ctypes.c_void_p()
+    assert lib.lbm_graph_create(None, None, 2, ctypes.byref(g)) == _lib.LBM_EINVAL
+    assert lib.lbm_graph_create(None, h, 2, ctypes.byref(g)) == _lib.LBM_EINVAL  # no members
+    assert lib.lbm_graph_launch(None, 1) == _lib.LBM_EINVAL
+    lib.lbm_batch_destroy(h)
+    lib.lbm_batch_destroy(None)
+    lib.lbm_graph_destroy(None)

@@ -1,0 +1,44 @@
+"""Host-side logic of the serving loop (CPU only): the request generator and the
+slot / HBM-budget admission accounting."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2302_04741_amd import serve
+
+
+def test_request_stream_matches_the_serving_recipe():
+    reqs = serve.make_requests(n=256)
+    assert len(reqs) == 256
+    t = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(t) > 0)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 1 / 20.0) < 0.01  # Poisson at 20/s
+    L = np.array([r.workload.dims[0] for r in reqs])
+    assert L.min() >= 64 and L.max() <= 1024
+    assert all(r.workload.dims[0] == r.workload.dims[1] for r in reqs)
+    for r in reqs:
+        wl = r.workload
+        g = np.asarray(wl.force[1])
+        assert 1e-6 <= np.hypot(*g) <= 1e-4
+        assert 0.55 <= wl.tau_hat <= 1.0 and r.steps == 2000
+    # the stream is reproducible from its seed
+    again = serve.make_requests(n=256)
+    assert [r.arrival for r in again] == [r.arrival for r in reqs]
+
+
+def test_admission_by_slots_and_budget():
+    a = serve.Admission(max_slots=3, budget_bytes=100)
+    assert a.fits(60)
+    a.take(60)
+    assert not a.fits(50)  # budget
+    assert a.fits(40)
+    a.take(40)
+    a.release(60)
+    assert a.used == 40 and a.slots == 1
+    a.take(10)
+    a.take(10)
+    assert not a.fits(1)  # slots
+    with pytest.raises(AssertionError):
+        a.take(1)
