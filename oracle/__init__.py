@@ -80,11 +80,11 @@ def lib(prec: str = "f64"):
         L.oracle_force.argtypes = [_int, _int, R, _ptr, R, _ptr, _ptr, _ptr]
         L.oracle_init.argtypes = [_int, _i64, _i64, _i64, _int, _int,
                                   _ptr, _ptr, _ptr, _ptr, _ptr, _int]
-        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, R, _int, _int,
+        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, R, R, _int, _int,
                                   _ptr, _ptr, _ptr, _i64, _int]
         L.oracle_moments.argtypes = [_int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _int]
-        L.oracle_sigma.argtypes = [_int, _i64, R, _int, _ptr, _ptr, _ptr, _int]
-        L.oracle_heat_flux.argtypes = [_int, _i64, R, _int, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_sigma.argtypes = [_int, _i64, R, R, _int, _ptr, _ptr, _ptr, _int]
+        L.oracle_heat_flux.argtypes = [_int, _i64, R, R, _int, _int, _ptr, _ptr, _ptr, _int]
         L.oracle_totals.argtypes = [_int, _i64, _ptr, _ptr]
         L.oracle_num_threads.argtypes = [_int]
         _libs[prec] = L
@@ -192,7 +192,7 @@ class OracleSim:
 
     def __init__(self, lat: int, dims, tau_hat: float, rho, u, theta, g,
                  eq_order: int = 0, force_order: int = 4, nthreads: int = 0,
-                 prec: str = "f64"):
+                 prec: str = "f64", mu: float = 0.0):
         self.lat = lat
         self.D = DIM[lat]
         self.prec = prec
@@ -203,6 +203,8 @@ class OracleSim:
         self.N = nx * ny * nz
         self.Q = len(lattice(lat)[0])
         self.tau_hat = float(tau_hat)
+        # mu > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (Sec. 3)
+        self.mu = float(mu)
         self.eq_order = eq_order
         self.force_order = force_order
         self.nthreads = nthreads
@@ -224,7 +226,7 @@ class OracleSim:
         self.g = np.ascontiguousarray(g.reshape(self.D, self.N).astype(self.dt))
 
     def step(self, n: int = 1):
-        _check(self.L.oracle_step(self.lat, *self.dims, self.tau_hat, self.eq_order,
+        _check(self.L.oracle_step(self.lat, *self.dims, self.tau_hat, self.mu, self.eq_order,
                                   self.force_order, _p(self.g), _p(self.f), _p(self._tmp),
                                   int(n), self.nthreads), "step")
         self.time += int(n)
@@ -240,14 +242,14 @@ class OracleSim:
     def sigma(self):
         N, D = self.N, self.D
         s = np.zeros((D, D, N), self.dt)
-        _check(self.L.oracle_sigma(self.lat, N, self.tau_hat, self.eq_order, _p(self.f),
+        _check(self.L.oracle_sigma(self.lat, N, self.tau_hat, self.mu, self.eq_order, _p(self.f),
                                    _p(self.g), _p(s), self.nthreads), "sigma")
         return s.astype(np.float64)
 
     def heat_flux(self):
         N, D = self.N, self.D
         q = np.zeros((D, N), self.dt)
-        _check(self.L.oracle_heat_flux(self.lat, N, self.tau_hat, self.eq_order,
+        _check(self.L.oracle_heat_flux(self.lat, N, self.tau_hat, self.mu, self.eq_order,
                                        self.force_order, _p(self.f), _p(self.g), _p(q),
                                        self.nthreads), "heat_flux")
         return q.astype(np.float64)

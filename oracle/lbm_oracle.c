@@ -29,6 +29,10 @@
  *   moments .................... eq. (rut1) plus the mid-point shift.
  *   heat flux .................. q = 1/2 sum_i f_i |xi_i-u|^2 (xi_i-u), Sec. 2
  *                                (the definition used for q_err).
+ *   per-cell relaxation time ... Sec. 3: tau = mu/(rho theta) keeps the dynamic
+ *                                viscosity and the conductivity constant; with
+ *                                tau^ = tau + 1/2 and the cell's mid-point rho and
+ *                                theta of the same step (mu > 0 selects it).
  *
  * Readings where the paper is silent or garbled (all documented in the design
  * notes of the repository):
@@ -485,12 +489,22 @@ static int eq_order_of(const or_lattice *L, int eq_order)
     return eq_order;
 }
 
+/* Relaxation time of one cell: the run's constant tau^, or, when a dynamic
+ * viscosity mu > 0 is given, tau^ = mu/(rho theta) + 1/2 from the cell's
+ * mid-point density and temperature (Sec. 3; tau^ = tau + 1/2 as in eq. (lbm)). */
+static real cell_tau_hat(real tau_hat, real mu, real rho, real theta)
+{
+    if (mu > 0.0) return mu / (rho * theta) + 0.5;
+    return tau_hat;
+}
+
 /* One collision: pre-collision f (stored variable) -> post-collision fs. */
 static void collide_cell(const or_lattice *L, int N, int nf, int with_sigma,
-                         real tau_hat, const real *f, const real *g, real *fs)
+                         real tau_hat, real mu, const real *f, const real *g, real *fs)
 {
     real rho, ub[3] = {0, 0, 0}, theta, feq[OR_MAXQ], F[OR_MAXQ], sig[9];
     cell_moments(L, f, g, &rho, ub, &theta);
+    tau_hat = cell_tau_hat(tau_hat, mu, rho, theta);
     equilibrium(L, N, rho, ub, theta, feq);
     if (with_sigma) cell_sigma(L, f, feq, ub, tau_hat, sig);
     body_force(L, nf, with_sigma, rho, ub, theta, g, sig, F);
@@ -617,15 +631,16 @@ static int64_t wrap(int64_t v, int64_t n)
 }
 
 /* nsteps collide-then-push steps; f holds the result, tmp is scratch. */
-int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, real tau_hat, int eq_order,
-                int force_order, const real *g, real *f, real *tmp, int64_t nsteps,
-                int nthreads)
+/* mu = 0: constant tau_hat; mu > 0: per-cell tau^ = mu/(rho theta) + 1/2. */
+int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, real tau_hat, real mu,
+                int eq_order, int force_order, const real *g, real *f, real *tmp,
+                int64_t nsteps, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (check_grid(L, nx, ny, nz)) return -1;
     int N = eq_order_of(L, eq_order), nf, ws;
     if (N < 0 || force_terms(force_order, &nf, &ws)) return -2;
-    if (!(tau_hat > 0.5)) return -3;
+    if (!(mu >= 0.0) || (mu == 0.0 && !(tau_hat > 0.5))) return -3;
     int64_t ncell = nx * ny * nz;
     int D = L->D, Q = L->Q;
     set_threads(nthreads);
@@ -636,7 +651,7 @@ int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, real tau_hat, i
             int64_t x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
             real gg[3] = {0, 0, 0}, fs[OR_MAXQ];
             for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + cell];
-            collide_cell(L, N, nf, ws, tau_hat, &src[cell * Q], gg, fs);
+            collide_cell(L, N, nf, ws, tau_hat, mu, &src[cell * Q], gg, fs);
             for (int i = 0; i < Q; ++i) {
                 int64_t xd = wrap(x + L->c[i][0], nx);
                 int64_t yd = wrap(y + L->c[i][1], ny);
@@ -673,8 +688,8 @@ int oracle_moments(int lattice, int64_t ncell, const real *f, const real *g,
 }
 
 /* Mid-point deviatoric stress of every cell: sigma[(a*D+b)*N + cell]. */
-int oracle_sigma(int lattice, int64_t ncell, real tau_hat, int eq_order, const real *f,
-                 const real *g, real *sigma, int nthreads)
+int oracle_sigma(int lattice, int64_t ncell, real tau_hat, real mu, int eq_order,
+                 const real *f, const real *g, real *sigma, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
@@ -688,7 +703,7 @@ int oracle_sigma(int lattice, int64_t ncell, real tau_hat, int eq_order, const r
         for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + x];
         cell_moments(L, &f[x * Q], gg, &r, ub, &t);
         equilibrium(L, N, r, ub, t, feq);
-        cell_sigma(L, &f[x * Q], feq, ub, tau_hat, sig);
+        cell_sigma(L, &f[x * Q], feq, ub, cell_tau_hat(tau_hat, mu, r, t), sig);
         for (int k = 0; k < D * D; ++k) sigma[k * ncell + x] = sig[k];
     }
     return 0;
@@ -696,15 +711,14 @@ int oracle_sigma(int lattice, int64_t ncell, real tau_hat, int eq_order, const r
 
 /* Heat flux q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical
  * distribution f = f0bar + (1 - 1/(2 tau^)) (f~ - f0bar + Fbar/2). */
-int oracle_heat_flux(int lattice, int64_t ncell, real tau_hat, int eq_order, int force_order,
-                     const real *f, const real *g, real *q, int nthreads)
+int oracle_heat_flux(int lattice, int64_t ncell, real tau_hat, real mu, int eq_order,
+                     int force_order, const real *f, const real *g, real *q, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (!L || ncell < 1) return -1;
     int N = eq_order_of(L, eq_order), nf, ws;
     if (N < 0 || force_terms(force_order, &nf, &ws)) return -2;
     int D = L->D, Q = L->Q;
-    real cf = 1.0 - 1.0 / (2.0 * tau_hat);
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < ncell; ++x) {
@@ -713,8 +727,10 @@ int oracle_heat_flux(int lattice, int64_t ncell, real tau_hat, int eq_order, int
         const real *fx = &f[x * Q];
         for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + x];
         cell_moments(L, fx, gg, &r, ub, &t);
+        real th_cell = cell_tau_hat(tau_hat, mu, r, t);
+        real cf = 1.0 - 1.0 / (2.0 * th_cell);
         equilibrium(L, N, r, ub, t, feq);
-        if (ws) cell_sigma(L, fx, feq, ub, tau_hat, sig);
+        if (ws) cell_sigma(L, fx, feq, ub, th_cell, sig);
         body_force(L, nf, ws, r, ub, t, gg, sig, F);
         for (int i = 0; i < Q; ++i) {
             real fp = feq[i] + cf * (fx[i] - feq[i] + 0.5 * F[i]);

@@ -14,6 +14,12 @@
   term changes the heat flux by q_err.
 * Initial state reproduces the input moments; results do not depend on the
   number of threads.
+* Per-cell relaxation time tau = mu/(rho theta) (Sec. 3, used there to keep the
+  dynamic viscosity constant): the shear-wave rate is mu/rho at any temperature;
+  in a gas whose pressure varies by +-15% the local stress is mu grad u at every
+  cell (while the constant-tau scheme gives (tau-hat - 1/2) p grad u); a
+  uniform state reduces to the constant-tau run with tau-hat = mu/(rho theta)
+  + 1/2; q_err holds with tau = mu/(rho theta).
 """
 import math
 
@@ -89,14 +95,14 @@ def test_global_invariants_ragged_grid(oracle_mod, lat, dims):
         assert abs((tot1[1 + D] - tot0[1 + D]) - de) < 1e-13 * tot0[1 + D]
 
 
-def shear_wave_rate(oracle_mod, lat, L, tau_hat, theta=1.0):
+def shear_wave_rate(oracle_mod, lat, L, tau_hat, theta=1.0, rho=1.0, mu=0.0):
     D = oracle_mod.DIM[lat]
     y = np.arange(L)
     s = np.sin(2 * np.pi * y / L)
     u = np.zeros((D, L))
     u[0] = 1e-4 * s
     dims = (1, L, 1)
-    sim = oracle_mod.OracleSim(lat, dims, tau_hat, 1.0, u, theta, np.zeros(D))
+    sim = oracle_mod.OracleSim(lat, dims, tau_hat, rho, u, theta, np.zeros(D), mu=mu)
     sim.step(200)  # let the initial non-equilibrium transient decay
     amps = []
     for _ in range(3):
@@ -201,3 +207,81 @@ def test_parity_workload_runs_stably(oracle_mod):
     assert abs(sim.totals()[0] - m0) < 1e-12 * m0
     # the uniform force accelerates the mean flow: sum rho u grows by n * sum rho g
     np.testing.assert_allclose((r * u[0]).sum(), 200 * 1e-5 * m0, rtol=1e-9)
+
+
+@pytest.mark.parametrize("lat,theta,rho", [(0, 0.8, 1.0), (0, 1.3, 1.0), (0, 1.0, 1.25),
+                                           (1, 1.3, 1.0)])
+def test_viscosity_mode_shear_wave_rate_is_mu_over_rho(oracle_mod, lat, theta, rho):
+    mu, L = 0.35, 64
+    r = oracle_mod.lattice(lat)[2]
+    k = 2 * np.pi / L / r
+    # tau_hat is ignored when mu > 0
+    rate = shear_wave_rate(oracle_mod, lat, L, 0.0, theta, rho, mu)
+    assert abs(rate / (mu / rho * k * k) - 1.0) < 3e-3
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_viscosity_mode_uniform_state_reduces_to_constant_tau(oracle_mod, lat):
+    D = oracle_mod.DIM[lat]
+    rho0, th0, mu = 1.2, 0.9, 0.4
+    u0 = np.array([0.05, -0.03, 0.02][:D]).reshape(D, 1)
+    g = np.array([1e-5, -2e-5, 3e-5][:D])
+    a = oracle_mod.OracleSim(lat, (1, 1, 1), 0.0, rho0, u0, th0, g, mu=mu)
+    b = oracle_mod.OracleSim(lat, (1, 1, 1), mu / (rho0 * th0) + 0.5, rho0, u0, th0, g)
+    a.step(50)
+    b.step(50)
+    np.testing.assert_allclose(a.f, b.f, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(a.heat_flux(), b.heat_flux(), rtol=1e-10, atol=1e-18)
+
+
+def test_viscosity_mode_stress_is_mu_grad_u_where_pressure_varies(oracle_mod):
+    """1-D gas with theta = 1 + 0.2 sin(2 pi x / 64) at rho = 1 (pressure varies
+    +-15% and oscillates acoustically) carrying a transverse shear u_y(x).  The
+    local Newtonian law sigma_xy = mu du_y/dx must hold at every cell with the
+    constant mu; with a constant tau-hat it holds with (tau-hat - 1/2) p(x)."""
+    lat, D, L = 0, 2, 64
+    r = oracle_mod.lattice(lat)[2]
+    x = np.arange(L)
+    theta = 1 + 0.2 * np.sin(2 * np.pi * x / L)
+    u = np.zeros((D, L))
+    u[1] = 1e-4 * np.sin(2 * np.pi * 2 * x / L)
+    kk = 2 * np.pi * np.fft.fftfreq(L) / r  # the lattice spacing is r
+
+    def ddx(f):
+        return np.real(np.fft.ifft(1j * kk * np.fft.fft(f)))
+
+    mu, tau_hat = 0.3, 0.8
+    for n in (5, 20, 60):
+        out = {}
+        for mode in ("mu", "tau"):
+            sim = oracle_mod.OracleSim(lat, (L, 1, 1), tau_hat, 1.0, u, theta, np.zeros(D),
+                                       mu=mu if mode == "mu" else 0.0)
+            sim.step(n)
+            rho, uu, th = sim.moments()
+            du = ddx(uu[1])
+            sel = np.abs(du) > 0.5 * np.abs(du).max()
+            out[mode] = (sim.sigma()[0, 1][sel] / du[sel], (rho * th)[sel])
+        ratio, p = out["mu"]
+        assert p.max() / p.min() > 1.15
+        assert np.abs(ratio / mu - 1).max() < 1.5e-2
+        ratio_t, p_t = out["tau"]
+        assert np.abs(ratio_t / ((tau_hat - 0.5) * p_t) - 1).max() < 1.5e-2
+        # the two schemes differ by the local pressure
+        assert np.abs(ratio_t / (tau_hat - 0.5) - ratio / mu).max() > 0.1
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_viscosity_mode_q_err(oracle_mod, lat):
+    D = oracle_mod.DIM[lat]
+    mu = 0.25
+    u0 = np.array([0.1, 0.05, -0.04][:D])
+    g = np.array([1e-5, -2e-5, 1.5e-5][:D])
+    q = {}
+    for order in (2, 4):
+        sim = oracle_mod.OracleSim(lat, (1, 1, 1), 0.0, 1.1, u0.reshape(D, 1), 1.2, g,
+                                   force_order=order, mu=mu)
+        sim.step(60)
+        q[order] = sim.heat_flux()[:, 0]
+        rho, u, theta = sim.moments()
+    ref = q_err_printed(D, rho[0], u[:, 0], theta[0], g, mu / (rho[0] * theta[0]))
+    np.testing.assert_allclose(q[2] - q[4], ref, rtol=1e-4, atol=0)
