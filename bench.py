@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -152,6 +154,140 @@ def cpu_baseline(wl, steps: int):
                       "(%.1f s, init excluded)" % (*wl.dims, steps, dt)}
 
 
+def _grid_mix(kind: str, count: int, seed: int):
+    """Workloads of a batch measurement: `serve` takes the grids, forces and
+    fields of the first `count` requests of the serving stream (D2Q37,
+    L ~ U{64..1024}); `small` draws `count` D2Q37 grids with L ~ U{32..256}
+    from the same recipe."""
+    from paper_2302_04741_amd import serve
+
+    if kind == "serve":
+        reqs = serve.make_requests(n=count, seed=seed)
+    else:
+        reqs = serve.make_requests(n=count, seed=seed, lmin=32, lmax=256)
+    return [r.workload for r in reqs]
+
+
+def bench_batch(args) -> dict:
+    """Aggregate MLUPS of a mix of independent D2Q37 FP32 grids: every grid
+    stepped alone with the single-grid kernel, one after another (sequential),
+    against all of them advanced together by the persistent multi-grid kernel
+    (one launch per step), eager and replayed from a captured graph."""
+    import torch
+
+    from paper_2302_04741_amd import sim as lbm_sim
+
+    wls = _grid_mix(args.mix, args.count, args.seed)
+    # a stream of its own: graph capture cannot run on the legacy default stream
+    stream = torch.cuda.Stream()
+    sims = [lbm_sim.from_workload(wl, storage=args.storage, stream=stream) for wl in wls]
+    cells = sum(wl.ncell for wl in wls)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def sequential(n):
+        for s in sims:
+            s.step(n)
+
+    ms_seq = timed(sequential)
+    b = lbm_sim.Batch(len(sims), stream=stream)
+    b.set(sims)
+    if args.batch_threads or args.batch_blocks:
+        b.set_launch(args.batch_threads, args.batch_blocks)
+    ms_batch = timed(b.step)
+    gsteps = 20
+    g = lbm_sim.Graph(b, gsteps)
+
+    def graph(n):
+        assert n % gsteps == 0
+        g.launch(n // gsteps)
+
+    ms_graph = timed(graph)
+    g.close()
+    b.close()
+    finite = all(np.isfinite(s.totals()).all() for s in sims)
+    for s in sims:
+        s.close()
+
+    def rate(ms):
+        return round(cells * args.steps / (ms * 1e-3) / 1e6, 1)
+
+    return {
+        "metric": "aggregate MLUPS of a batch of independent grids",
+        "value": rate(ms_batch),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": "%d D2Q37 grids (%s mix, seed %d), %d cells in all, %s storage"
+                               % (len(wls), args.mix, args.seed, cells, args.storage.upper()),
+                   "grids": [list(wl.dims[:2]) for wl in wls]},
+        "sequential_mlups": rate(ms_seq),
+        "batched_mlups": rate(ms_batch),
+        "batched_graph_mlups": rate(ms_graph),
+        "speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+        "finite": bool(finite),
+    }
+
+
+def bench_serve(args) -> dict:
+    """The serving stream: 256 D2Q37 requests, Poisson arrivals at 20/s, 2000
+    steps each, served by continuous batching under an HBM budget; latency run
+    in real time, then a throughput run with every request queued at t = 0,
+    and the same requests solved one after another with the single-grid
+    kernel."""
+    from paper_2302_04741_amd import serve
+
+    reqs = serve.make_requests(n=args.count, rate=args.rate, seed=args.seed, steps=args.req_steps)
+    budget = int(args.budget_gib * (1 << 30))
+    srv = serve.Server(storage=args.storage, max_slots=args.slots, budget_bytes=budget,
+                       chunk_steps=args.chunk)
+    live = srv.run(reqs, realtime=True)
+    print("serve: real-time run done in %.1f s" % live["wall_s"], file=sys.stderr, flush=True)
+    thr = serve.Server(storage=args.storage, max_slots=args.slots, budget_bytes=budget,
+                       chunk_steps=args.chunk).run(reqs, realtime=False)
+    print("serve: queued run done in %.1f s" % thr["wall_s"], file=sys.stderr, flush=True)
+    seq = serve.run_sequential(reqs, storage=args.storage)
+    print("serve: sequential run done in %.1f s" % seq["wall_s"], file=sys.stderr, flush=True)
+    return {
+        "metric": "served completion latency p50/p99 and aggregate MLUPS",
+        "value": round(live["p99_latency_s"], 4),
+        "unit": "s (p99 latency)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": "%d D2Q37 requests, Poisson %.0f/s (seed %d), L ~ U{64..1024}, "
+                               "%d steps each, %s storage, %d slots, %.1f GiB budget, "
+                               "%d-step chunks"
+                               % (args.count, args.rate, args.seed, args.req_steps,
+                                  args.storage.upper(), args.slots, args.budget_gib, args.chunk)},
+        "p50_latency_s": round(live["p50_latency_s"], 4),
+        "p99_latency_s": round(live["p99_latency_s"], 4),
+        "failed": live["failed"],
+        "max_concurrent": live["max_concurrent"],
+        "live_wall_s": round(live["wall_s"], 3),
+        "live_aggregate_mlups": round(live["aggregate_mlups"], 1),
+        "queued_aggregate_mlups": round(thr["aggregate_mlups"], 1),
+        "queued_max_concurrent": thr["max_concurrent"],
+        "queued_failed": thr["failed"],
+        "sequential_aggregate_mlups": round(seq["aggregate_mlups"], 1),
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +302,23 @@ def main(argv=None) -> int:
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary under profiles/ and exit (no GPU)")
+    ap.add_argument("--workload", default="step", choices=["step", "batch", "serve"],
+                    help="step: the fused step on one grid (default); batch: a mix of "
+                         "independent grids, batched vs sequential; serve: the request stream")
+    ap.add_argument("--mix", default="serve", choices=["serve", "small"],
+                    help="batch: grid sizes of the serving stream or small grids")
+    ap.add_argument("--count", type=int, default=0,
+                    help="batch: number of grids (default 64); serve: requests (default 256)")
+    ap.add_argument("--seed", type=int, default=4741)
+    ap.add_argument("--batch-threads", type=int, default=0,
+                    help="batch: tile width / threads per block (64, 128, 256; 0 = 256)")
+    ap.add_argument("--batch-blocks", type=int, default=0,
+                    help="batch: 0 = one block per tile, > 0 = persistent grid")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--req-steps", type=int, default=2000, help="serve: steps per request")
+    ap.add_argument("--slots", type=int, default=64, help="serve: concurrent requests")
+    ap.add_argument("--budget-gib", type=float, default=1.0, help="serve: HBM budget")
+    ap.add_argument("--chunk", type=int, default=100, help="serve: steps per batched chunk")
     args = ap.parse_args(argv)
 
     if args.summarize_pmc:
@@ -178,6 +331,16 @@ def main(argv=None) -> int:
               "(multi-GPU slab decomposition is a design, not built); run with --gpus 1",
               file=sys.stderr)
         return 2
+
+    if args.workload != "step":
+        if args.workload == "batch":
+            args.count = args.count or 64
+            out = bench_batch(args)
+        else:
+            args.count = args.count or 256
+            out = bench_serve(args)
+        print(json.dumps(out), flush=True)
+        return 0
 
     import torch
 

@@ -102,7 +102,9 @@ typedef struct {
 } lbm_params;
 
 /* Bytes of device workspace a handle needs for these parameters (256-byte
- * aligned sub-buffers included).  Returns 0 if the parameters are invalid. */
+ * aligned sub-buffers included): two population arrays of Q planes whose rows
+ * are padded to a multiple of 64 values, the force table, and the reduction
+ * scratch of lbm_totals.  Returns 0 if the parameters are invalid. */
 LBM_API size_t lbm_workspace_bytes(const lbm_params *p);
 
 /* Create a handle and initialise the populations from FP64 device fields.
@@ -168,9 +170,10 @@ LBM_API lbm_status lbm_totals(lbm_sim *s, double *out);
  * step (the quantity q_err of Sec. 2 refers to).  q: D*N device doubles. */
 LBM_API lbm_status lbm_heat_flux(lbm_sim *s, double *q);
 
-/* Raw population storage (lbm_population_bytes bytes, library layout: SoA
- * planes of h_i in the storage type, post-collision "pull" layout) for
- * checkpoint/restart: get copies out, set copies in (device buffers, async).
+/* Raw population state for checkpoint/restart: lbm_population_bytes bytes,
+ * dense SoA planes of h_i in the storage type, value i*N + cell (the padding
+ * of the internal rows is dropped), post-collision "pull" layout.  get copies
+ * out, set copies in (device buffers, async on the handle's stream).
  * Restoring a state together with lbm_set_step_count resumes bitwise. */
 LBM_API size_t lbm_population_bytes(const lbm_sim *s);
 LBM_API lbm_status lbm_get_populations(lbm_sim *s, void *dst);
@@ -185,20 +188,35 @@ LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
  * 512 or 1024).  0 restores the default.  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
+/* Relaxation time per cell (Sec. 3 of the paper: tau = mu/(rho theta) keeps the
+ * dynamic viscosity mu and the heat conductivity constant).  mu > 0: every
+ * step, the stress and the heat flux use tau^ = mu/(rho theta) + 1/2 with the
+ * cell's own mid-point rho and theta (tau^ = tau + 1/2 as in eq. (lbm)); the
+ * tau_hat of the parameters is ignored until mu is set back to 0.  mu is in
+ * the units of tau_hat * theta (time steps times reference temperature).
+ * Takes effect at the next step; batches and graphs that hold the handle must
+ * be rebuilt (they refuse to run stale).  LBM_EINVAL if mu < 0 or not finite. */
+LBM_API lbm_status lbm_set_viscosity(lbm_sim *s, double mu);
+
 /* ---- batching: several simulations per launch, and captured step loops ---- */
 
 typedef struct lbm_batch lbm_batch; /* opaque host handle */
 typedef struct lbm_graph lbm_graph; /* opaque host handle */
 
-/* Device workspace of a batch of up to max_sims simulations (its tile table). */
+/* Device workspace of a batch of up to max_sims simulations (its tile table:
+ * 8 * (max_sims + 1) bytes of tile offsets, rounded up to 256, then one
+ * descriptor per member). */
 LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
 
 /* A batch advances its member simulations together: every step is ONE launch
- * of a persistent multi-grid kernel whose blocks walk a list of tiles (one
- * tile = one grid row of one member) with a fixed stride.  Members must share
- * lattice, storage, eq_order and force_order; grid sizes, tau_hat, rho0 and
- * forces may differ.  The per-cell arithmetic is that of lbm_step, so a
- * member's result does not depend on the other members.  Runs on hip_stream. */
+ * of a multi-grid kernel over a list of tiles spanning all members (one tile =
+ * a run of `threads` cells along x in one grid row of one member).  By default
+ * each tile is one block and the hardware balances uneven members; with a
+ * block count set, a persistent grid walks the list with a fixed stride.
+ * Members must share lattice, storage, eq_order and force_order; grid sizes,
+ * tau_hat, mu, rho0 and forces may differ.  The per-cell arithmetic is that of
+ * lbm_step, so a member's result does not depend on the other members or on
+ * the launch shape.  Runs on hip_stream. */
 LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
                                     void *hip_stream, lbm_batch **out);
 
@@ -211,8 +229,13 @@ LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t cou
 /* Advance every member by nsteps (>= 0) steps, one launch per step. */
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
-/* Persistent grid of the multi-grid kernel: blocks of 256 threads (0 = default). */
-LBM_API lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
+/* Launch shape of the multi-grid kernel.  threads: tile width and threads per
+ * block, 64, 128 or 256 (0 = 256); blocks: 0 = one block per tile (default),
+ * > 0 = a persistent grid of that many blocks (at most 2^31 - 1).  A new tile
+ * width rebuilds the tile table from the members' current state (LBM_EINVAL,
+ * and the batch must be set again, if a member went stale).  Graphs captured
+ * before must be captured again. */
+LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks);
 
 /* NULL-safe; does not free the workspace and does not wait for queued work. */
 LBM_API void lbm_batch_destroy(lbm_batch *b);

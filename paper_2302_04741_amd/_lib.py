@@ -30,8 +30,9 @@ API_SYMBOLS = (
     "lbm_workspace_bytes", "lbm_create", "lbm_set_force", "lbm_step", "lbm_moments",
     "lbm_destroy", "lbm_last_error", "lbm_totals", "lbm_heat_flux", "lbm_population_bytes",
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
-    "lbm_set_stream", "lbm_set_block", "lbm_batch_workspace_bytes", "lbm_batch_create",
-    "lbm_batch_set", "lbm_batch_step", "lbm_batch_set_blocks", "lbm_batch_destroy",
+    "lbm_set_stream", "lbm_set_block", "lbm_set_viscosity", "lbm_batch_workspace_bytes",
+    "lbm_batch_create", "lbm_batch_set", "lbm_batch_step", "lbm_batch_set_launch",
+    "lbm_batch_destroy",
     "lbm_graph_create", "lbm_graph_launch", "lbm_graph_destroy", "lbm_lattice_table",
     "lbm_version",
 )
@@ -109,6 +110,8 @@ def load() -> ctypes.CDLL:
     L.lbm_set_stream.restype = _i32
     L.lbm_set_block.argtypes = [_vp, _i32]
     L.lbm_set_block.restype = _i32
+    L.lbm_set_viscosity.argtypes = [_vp, ctypes.c_double]
+    L.lbm_set_viscosity.restype = _i32
     L.lbm_batch_workspace_bytes.argtypes = [_i32]
     L.lbm_batch_workspace_bytes.restype = _sz
     L.lbm_batch_create.argtypes = [_i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]
@@ -117,8 +120,8 @@ def load() -> ctypes.CDLL:
     L.lbm_batch_set.restype = _i32
     L.lbm_batch_step.argtypes = [_vp, _i64]
     L.lbm_batch_step.restype = _i32
-    L.lbm_batch_set_blocks.argtypes = [_vp, _i32]
-    L.lbm_batch_set_blocks.restype = _i32
+    L.lbm_batch_set_launch.argtypes = [_vp, _i32, _i64]
+    L.lbm_batch_set_launch.restype = _i32
     L.lbm_batch_destroy.argtypes = [_vp]
     L.lbm_batch_destroy.restype = None
     L.lbm_graph_create.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_vp)]

@@ -2,8 +2,8 @@
 
 * Single-grid step: threads per block (64 ... 1024) per (lattice, storage,
   equilibrium order, force order, grid class).
-* Multi-grid (batched) step: number of persistent blocks per (lattice, storage,
-  orders, batch class).
+* Multi-grid (batched) step: tile width and grid (one block per tile or a
+  persistent grid) per (lattice, storage, orders, batch class).
 
 Candidates are timed with HIP events on scratch simulations of the same shape
 (smooth synthetic fields; the cost of a step does not depend on the data), so
@@ -18,7 +18,8 @@ import os
 import threading
 
 BLOCK_CANDIDATES = (64, 128, 256, 512, 1024)
-BATCH_CANDIDATES = (512, 1024, 2048, 4096, 8192)
+# (threads per block = tile width, blocks: 0 = one per tile, else persistent)
+BATCH_CANDIDATES = ((64, 0), (128, 0), (256, 0), (256, 1280), (256, 2560), (64, 5120))
 
 _lock = threading.Lock()
 
@@ -77,13 +78,13 @@ def _time_steps(torch, step, stream, steps: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def _scratch(lattice, dims, storage, eq_order, force_order, seed=0):
+def _scratch(lattice, dims, storage, eq_order, force_order, seed=0, stream=None):
     from . import sim, workloads
 
     wl = workloads.random_smooth(lattice, tuple(dims), seed=seed, force_kind="uniform",
                                  force_order=force_order)
     wl.eq_order = eq_order
-    return sim.from_workload(wl, storage=storage)
+    return sim.from_workload(wl, storage=storage, stream=stream)
 
 
 def block_key(lattice, storage, eq_order, force_order, dims) -> str:
@@ -118,29 +119,32 @@ def batch_key(lattice, storage, eq_order, force_order, dims_list) -> str:
                                          batch_class(dims_list))
 
 
-def tune_batch_blocks(lattice: str, dims_list, storage: str = "f32", eq_order: int = 0,
-                      force_order: int = 4, steps: int = 10, retune: bool = False) -> int:
-    """Fastest persistent grid of the multi-grid kernel for this class of batch."""
+def tune_batch_launch(lattice: str, dims_list, storage: str = "f32", eq_order: int = 0,
+                      force_order: int = 4, steps: int = 10, retune: bool = False):
+    """Fastest (threads, blocks) launch of the multi-grid kernel for this class
+    of batch (cached)."""
     key = batch_key(lattice, storage, eq_order, force_order, dims_list)
     if not retune:
         hit = _load_cache().get(key)
         if hit:
-            return int(hit["blocks"])
+            return tuple(hit["launch"])
     import torch
 
     from . import sim
 
-    sims = [_scratch(lattice, d, storage, eq_order, force_order, seed=k)
+    stream = torch.cuda.Stream()
+    sims = [_scratch(lattice, d, storage, eq_order, force_order, seed=k, stream=stream)
             for k, d in enumerate(dims_list)]
-    b = sim.Batch(len(sims))
+    b = sim.Batch(len(sims), stream=stream)
     b.set(sims)
     times = {}
-    for nb in BATCH_CANDIDATES:
-        b.set_blocks(nb)
-        times[nb] = _time_steps(torch, b.step, b.stream, steps)
+    for threads, blocks in BATCH_CANDIDATES:
+        b.set_launch(threads, blocks)
+        times["%d/%d" % (threads, blocks)] = _time_steps(torch, b.step, stream, steps)
     b.close()
     for s in sims:
         s.close()
     best = min(times, key=times.get)
-    _store(key, {"blocks": best, "ms_per_step": times})
-    return best
+    launch = tuple(int(v) for v in best.split("/"))
+    _store(key, {"launch": list(launch), "ms_per_step": times})
+    return launch

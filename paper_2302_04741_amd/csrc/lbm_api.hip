@@ -78,12 +78,15 @@ struct Layout {
     size_t off_pop1, off_gtab, off_part, off_tot, total;
 };
 
+int64_t row_pitch(int64_t nx) { return (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
+
 Layout layout_of(const lbm_params *p)
 {
     Layout L{};
     const int D = lattice_dim(p->lattice), Q = lattice_q(p->lattice);
     const size_t N = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
-    L.pop = align_up(size_t(Q) * N * storage_bytes(p->storage));
+    const size_t P = size_t(row_pitch(p->nx)) * size_t(p->ny) * size_t(p->nz);
+    L.pop = align_up(size_t(Q) * P * storage_bytes(p->storage));
     int64_t ext = p->nx > p->ny ? p->nx : p->ny;
     ext = ext > p->nz ? ext : p->nz;
     size_t gcount = size_t(D) * size_t(ext);
@@ -119,10 +122,10 @@ lbm_status check_params(const lbm_params *p)
         return fail(LBM_EINVAL, "D2Q37 needs nz == 1 (got %lld)", (long long)p->nz);
     if (p->nx > (int64_t(1) << 30) || p->ny > 65535 || p->nz > 65535)
         return fail(LBM_EUNSUPPORTED, "grid extents limited to nx <= 2^30, ny, nz <= 65535");
-    const double cells = double(p->nx) * double(p->ny) * double(p->nz);
-    if (cells * double(storage_bytes(p->storage)) >= 4294967296.0)
+    const double plane = double(row_pitch(p->nx)) * double(p->ny) * double(p->nz);
+    if (plane * double(storage_bytes(p->storage)) >= 4294967296.0)
         return fail(LBM_EUNSUPPORTED,
-                    "one population plane (nx*ny*nz values) must stay below 4 GiB");
+                    "one population plane (rows padded to 64 values) must stay below 4 GiB");
     if (!std::isfinite(p->tau_hat) || !(p->tau_hat > 0.5))
         return fail(LBM_EINVAL, "tau_hat must be finite and > 0.5 (got %g)", p->tau_hat);
     if (p->eq_order < 0 || p->eq_order == 1)
@@ -173,8 +176,9 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->Q = lattice_q(p->lattice);
     s->eq = p->eq_order ? p->eq_order : lattice_maxeq(p->lattice);
     s->N = p->nx * p->ny * p->nz;
-    s->gd = GridDims{int32_t(p->nx), int32_t(p->ny), int32_t(p->nz), 0, s->N};
-    s->co = StepCoef{1.0 / p->tau_hat, 1.0 - 0.5 / p->tau_hat, p->rho0};
+    s->gd = GridDims{int32_t(p->nx), int32_t(p->ny), int32_t(p->nz), int32_t(row_pitch(p->nx)),
+                     s->N, row_pitch(p->nx) * p->ny * p->nz};
+    s->co = StepCoef{1.0 / p->tau_hat, 1.0 - 0.5 / p->tau_hat, p->rho0, 0.0};
     s->fd = ForceDesc{};
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->ws = static_cast<char *>(workspace);
@@ -329,8 +333,12 @@ lbm_status lbm_get_populations(lbm_sim *s, void *dst)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (!dst) return fail(LBM_EINVAL, "dst is NULL");
-    hipError_t e = hipMemcpyAsync(dst, s->pop[s->cur], lbm_population_bytes(s),
-                                  hipMemcpyDeviceToDevice, s->stream);
+    // dense rows out of the padded planes: one strided copy over Q*ny*nz rows
+    const size_t sb = storage_bytes(s->p.storage);
+    hipError_t e = hipMemcpy2DAsync(dst, size_t(s->gd.nx) * sb, s->pop[s->cur],
+                                    size_t(s->gd.px) * sb, size_t(s->gd.nx) * sb,
+                                    size_t(s->Q) * size_t(s->gd.ny) * size_t(s->gd.nz),
+                                    hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return dev_fail(e, "population copy");
     return ok();
 }
@@ -339,8 +347,11 @@ lbm_status lbm_set_populations(lbm_sim *s, const void *src)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (!src) return fail(LBM_EINVAL, "src is NULL");
-    hipError_t e = hipMemcpyAsync(s->pop[s->cur], src, lbm_population_bytes(s),
-                                  hipMemcpyDeviceToDevice, s->stream);
+    const size_t sb = storage_bytes(s->p.storage);
+    hipError_t e = hipMemcpy2DAsync(s->pop[s->cur], size_t(s->gd.px) * sb, src,
+                                    size_t(s->gd.nx) * sb, size_t(s->gd.nx) * sb,
+                                    size_t(s->Q) * size_t(s->gd.ny) * size_t(s->gd.nz),
+                                    hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return dev_fail(e, "population copy");
     return ok();
 }
@@ -374,6 +385,16 @@ lbm_status lbm_set_block(lbm_sim *s, int32_t threads)
     return ok();
 }
 
+lbm_status lbm_set_viscosity(lbm_sim *s, double mu)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!(mu >= 0.0) || !std::isfinite(mu))
+        return fail(LBM_EINVAL, "mu must be finite and >= 0 (got %g)", mu);
+    s->co.mu = mu;
+    s->gen++;
+    return ok();
+}
+
 int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
 {
     if (lattice != LBM_D2Q37 && lattice != LBM_D3Q39)
@@ -389,7 +410,7 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.2.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.3.0"; }
 
 // ---------------------------------------------------------------------------
 // batches
@@ -399,14 +420,18 @@ const char *lbm_version(void) { return "lbm-gfx950 0.2.0"; }
 struct lbm_batch {
     int32_t max_sims;
     hipStream_t stream;
-    TileSim *table;  // device, in the caller's workspace
+    char *ws;        // device workspace: begin[max_sims + 1], then TileSim[max_sims]
+    int64_t *begin;  // device: first tile of each member
+    TileSim *table;  // device: the members
     std::vector<lbm_sim *> sims;
     std::vector<int64_t> step_at_set;  // members' step counts when the table was built
     std::vector<int64_t> gen_at_set;   // members' launch-argument generations then
-    int64_t generation;                // bumped by every lbm_batch_set
+    std::vector<char> host;            // staging copy of the uploaded table
+    int64_t generation;                // bumped whenever the table or launch shape changes
     int64_t steps_done;                // batch steps since the table was built
     int64_t ntiles;
-    int blocks;
+    int threads;     // tile width and block size
+    int64_t blocks;  // 0: one block per tile
 };
 
 struct lbm_graph {
@@ -422,7 +447,9 @@ struct lbm_graph {
 };
 
 namespace {
-constexpr int BATCH_DEFAULT_BLOCKS = 2048;
+constexpr int BATCH_DEFAULT_THREADS = 256;
+
+size_t batch_begin_bytes(int32_t max_sims) { return align_up(size_t(max_sims + 1) * 8); }
 
 lbm_status batch_check(const lbm_batch *b)
 {
@@ -442,11 +469,67 @@ lbm_status batch_launch(lbm_batch *b, int64_t nsteps)
     const lbm_sim *s0 = b->sims[0];
     for (int64_t k = 0; k < nsteps; ++k) {
         const int parity = int((b->steps_done + k) & 1);
+        const BatchLaunch bl{b->begin,  b->table,   int(b->sims.size()), b->ntiles,
+                             parity,    b->threads, b->blocks,           b->stream};
         hipError_t e = launch_multi_step(s0->p.lattice, s0->p.storage, s0->eq, s0->p.force_order,
-                                         b->table, int(b->sims.size()), b->ntiles, parity,
-                                         b->blocks, b->stream);
+                                         bl);
         if (e != hipSuccess) return dev_fail(e, "multi-grid step launch");
     }
+    return LBM_OK;
+}
+
+// Build the tile table of `sims` for the batch's tile width and upload it on
+// the batch's stream (the host staging copy lives in the batch, so the
+// asynchronous copy never reads freed memory).
+lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
+{
+    const size_t off = batch_begin_bytes(b->max_sims);
+    std::vector<char> host(off + size_t(count) * sizeof(TileSim), 0);
+    int64_t *begin = reinterpret_cast<int64_t *>(host.data());
+    TileSim *tab = reinterpret_cast<TileSim *>(host.data() + off);
+    int64_t tiles = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const lbm_sim *s = sims[k];
+        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
+        const lbm_sim *s0 = sims[0];
+        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
+            s->p.force_order != s0->p.force_order)
+            return fail(LBM_EINVAL,
+                        "batch members must share lattice, storage, eq_order and force_order");
+        TileSim &t = tab[k];
+        t.pop[0] = s->pop[0];
+        t.pop[1] = s->pop[1];
+        t.cur = s->cur;
+        t.chunks_x = int32_t((s->p.nx + b->threads - 1) / b->threads);
+        t.tile_begin = tiles;
+        t.gd = s->gd;
+        t.fd = s->fd;
+        t.co = s->co;
+        begin[k] = tiles;
+        tiles += int64_t(t.chunks_x) * s->p.ny * s->p.nz;
+    }
+    begin[count] = tiles;
+    // wait for the previous table's readers before overwriting the staging copy
+    if (!b->host.empty()) {
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return dev_fail(e, "stream synchronize");
+    }
+    b->host.swap(host);
+    hipError_t e = hipMemcpyAsync(b->ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e != hipSuccess) return dev_fail(e, "tile table upload");
+    b->sims.assign(sims, sims + count);
+    b->step_at_set.clear();
+    b->gen_at_set.clear();
+    for (lbm_sim *s : b->sims) {
+        b->step_at_set.push_back(s->step);
+        b->gen_at_set.push_back(s->gen);
+    }
+    b->steps_done = 0;
+    b->generation++;
+    b->ntiles = tiles;
     return LBM_OK;
 }
 
@@ -465,7 +548,7 @@ extern "C" {
 size_t lbm_batch_workspace_bytes(int32_t max_sims)
 {
     if (max_sims < 1 || max_sims > (1 << 20)) return 0;
-    return align_up(size_t(max_sims) * sizeof(TileSim));
+    return batch_begin_bytes(max_sims) + align_up(size_t(max_sims) * sizeof(TileSim));
 }
 
 lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
@@ -485,11 +568,14 @@ lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_
     if (!b) return fail(LBM_EINVAL, "out of host memory");
     b->max_sims = max_sims;
     b->stream = static_cast<hipStream_t>(hip_stream);
-    b->table = static_cast<TileSim *>(workspace);
+    b->ws = static_cast<char *>(workspace);
+    b->begin = reinterpret_cast<int64_t *>(b->ws);
+    b->table = reinterpret_cast<TileSim *>(b->ws + batch_begin_bytes(max_sims));
     b->steps_done = 0;
     b->ntiles = 0;
     b->generation = 0;
-    b->blocks = BATCH_DEFAULT_BLOCKS;
+    b->threads = BATCH_DEFAULT_THREADS;
+    b->blocks = 0;
     *out = b;
     return ok();
 }
@@ -500,42 +586,8 @@ lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count)
     if (!sims) return fail(LBM_EINVAL, "sims is NULL");
     if (count < 1 || count > b->max_sims)
         return fail(LBM_EINVAL, "count must be in [1, %d] (got %d)", b->max_sims, count);
-    std::vector<TileSim> host(static_cast<size_t>(count));
-    int64_t tiles = 0;
-    for (int32_t k = 0; k < count; ++k) {
-        const lbm_sim *s = sims[k];
-        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
-        for (int32_t j = 0; j < k; ++j)
-            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
-        const lbm_sim *s0 = sims[0];
-        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
-            s->p.force_order != s0->p.force_order)
-            return fail(LBM_EINVAL,
-                        "batch members must share lattice, storage, eq_order and force_order");
-        TileSim &t = host[size_t(k)];
-        t.pop[0] = s->pop[0];
-        t.pop[1] = s->pop[1];
-        t.cur = s->cur;
-        t.pad = 0;
-        t.tile_begin = tiles;
-        t.gd = s->gd;
-        t.fd = s->fd;
-        t.co = s->co;
-        tiles += int64_t(s->p.ny) * s->p.nz;
-    }
-    hipError_t e = hipMemcpyAsync(b->table, host.data(), host.size() * sizeof(TileSim),
-                                  hipMemcpyHostToDevice, b->stream);
-    if (e != hipSuccess) return dev_fail(e, "tile table upload");
-    b->sims.assign(sims, sims + count);
-    b->step_at_set.clear();
-    b->gen_at_set.clear();
-    for (lbm_sim *s : b->sims) {
-        b->step_at_set.push_back(s->step);
-        b->gen_at_set.push_back(s->gen);
-    }
-    b->steps_done = 0;
-    b->generation++;
-    b->ntiles = tiles;
+    lbm_status st = batch_build(b, sims, count);
+    if (st != LBM_OK) return st;
     return ok();
 }
 
@@ -552,11 +604,29 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     return ok();
 }
 
-lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks)
+lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks)
 {
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
-    if (blocks < 0 || blocks > (1 << 22)) return fail(LBM_EINVAL, "blocks out of range");
-    b->blocks = blocks ? blocks : BATCH_DEFAULT_BLOCKS;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
+        return fail(LBM_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", threads);
+    if (blocks < 0 || blocks > 0x7fffffff)
+        return fail(LBM_EINVAL, "blocks must be in [0, 2^31 - 1]");
+    const int th = threads ? threads : BATCH_DEFAULT_THREADS;
+    b->blocks = blocks;
+    b->generation++;
+    if (th != b->threads) {
+        b->threads = th;
+        if (!b->sims.empty()) {
+            // the tiles change with their width: rebuild from the members' state
+            if (batch_check(b) != LBM_OK) {
+                b->sims.clear();
+                return fail(LBM_EINVAL, "members went stale; call lbm_batch_set");
+            }
+            std::vector<lbm_sim *> members(b->sims);
+            lbm_status st = batch_build(b, members.data(), int32_t(members.size()));
+            if (st != LBM_OK) return st;
+        }
+    }
     return ok();
 }
 

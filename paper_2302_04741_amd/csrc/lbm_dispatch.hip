@@ -26,11 +26,9 @@ hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const TileSim *table, int nsims,
-                             int64_t ntiles, int parity, int blocks, hipStream_t stream)
+hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl)
 {
-#define LBM_MS(L, S) \
-    return launch_multi_step_ls<L, S>(eq, fo, table, nsims, ntiles, parity, blocks, stream)
+#define LBM_MS(L, S) return launch_multi_step_ls<L, S>(eq, fo, bl)
     if (lat == 0 && storage == 0) LBM_MS(0, double);
     if (lat == 0 && storage == 1) LBM_MS(0, float);
     if (lat == 0 && storage == 2) LBM_MS(0, __half);

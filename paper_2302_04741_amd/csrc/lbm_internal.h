@@ -149,10 +149,18 @@ template <class L> struct DevScale {
 // ---------------------------------------------------------------------------
 // argument blocks
 // ---------------------------------------------------------------------------
+// Population planes store rows of px >= nx values (nx rounded up to a multiple
+// of 64), so that every row starts on a 128-byte line and a wavefront's run of
+// 64 consecutive cells touches the fewest lines; values at x >= nx are never
+// read or written.  Field arrays (moments, forces) are dense: cell =
+// (z*ny + y)*nx + x.
+constexpr int ROW_ALIGN = 64;
+
 struct GridDims {
     int32_t nx, ny, nz;
-    int32_t pad;
-    int64_t N;  // nx*ny*nz
+    int32_t px;  // row pitch of the population planes
+    int64_t N;   // cells, nx*ny*nz
+    int64_t P;   // values per population plane, px*ny*nz
 };
 
 struct ForceDesc {
@@ -167,14 +175,16 @@ struct StepCoef {
     double om;   // 1/tau^
     double cf;   // 1 - 1/(2 tau^)
     double rho0; // reference density of the stored deviations
+    double mu;   // > 0: per-cell tau^ = mu/(rho theta) + 1/2 replaces om and cf
 };
 
-// One member of a multi-grid batch (device table entry).
+// One member of a multi-grid batch (device table entry).  Its tiles are runs
+// of blockDim.x cells along x: chunks_x per grid row, rows in (z, y) order.
 struct TileSim {
     const void *pop[2];  // the two population buffers
     int32_t cur;         // buffer holding the state when the table was built
-    int32_t pad;
-    int64_t tile_begin;  // first tile (grid row) of this simulation in the list
+    int32_t chunks_x;    // tiles per grid row, ceil(nx / tile width)
+    int64_t tile_begin;  // first tile of this simulation in the list
     GridDims gd;
     ForceDesc fd;
     StepCoef co;
@@ -225,6 +235,8 @@ template <class T> struct CellState {
     T th;        // mid-point temperature
     T g[3];
     T sig[3][3]; // mid-point deviatoric stress (traceless), zero unless needed
+    T om;        // 1/tau^ of this cell
+    T cf;        // 1 - 1/(2 tau^) of this cell
 };
 
 // Raw sums of one cell over the stored deviations h_i = f_i - w_i rho0:
@@ -268,19 +280,23 @@ __device__ __forceinline__ RawSums<T> raw_sums(const T (&h)[L::Q])
     return s;
 }
 
-// Mid-point moments and (if WITH_SIGMA) sigma-bar from the raw sums.
+// Mid-point moments, relaxation coefficients and (if WITH_SIGMA) sigma-bar
+// from the raw sums.
 //   rho = rho0 + drho, u = r j / rho + g/2,
 //   theta = (E/rho - |u~|^2 + |g|^2/4)/D with E = rho0 D + r^2 tr P;
+//   tau^ = the run's constant, or mu/(rho theta) + 1/2 when mu > 0 (the
+//   relaxation time that keeps the dynamic viscosity constant, Sec. 3);
 //   sigma-bar = -cf [sum f xi xi - rho(u u + theta delta) + rho (u g + g u)/2]
 //   with its trace removed.  The isotropic parts (rho0 delta and
 //   rho theta delta) drop out of the traceless projection exactly, so they are
 //   left out: sigma-bar = dev(-cf [r^2 P - rho u u + rho (u g + g u)/2]).
 template <class L, class T, bool WITH_SIGMA>
-__device__ __forceinline__ void finish_moments(const RawSums<T> &s, const T g[3], T cf, T rho0,
-                                               CellState<T> &cs)
+__device__ __forceinline__ void finish_moments(const RawSums<T> &s, const T g[3],
+                                               const StepCoef &co, CellState<T> &cs)
 {
     constexpr int D = L::D;
     const T r = T(L::R), r2 = T(L::R2);
+    const T rho0 = T(co.rho0);
     const T rho = rho0 + s.drho;
     const T inv = T(1) / rho;
     T ut2 = T(0), g2 = T(0), tr = T(0);
@@ -299,6 +315,13 @@ __device__ __forceinline__ void finish_moments(const RawSums<T> &s, const T g[3]
     }
     const T E = rho0 * T(D) + r2 * tr;
     cs.th = (E * inv - ut2 + T(0.25) * g2) * T(1.0 / D);
+    cs.om = T(co.om);
+    cs.cf = T(co.cf);
+    if (co.mu > 0.0) {  // uniform over the launch
+        cs.om = T(1) / (T(co.mu) / (rho * cs.th) + T(0.5));
+        cs.cf = T(1) - T(0.5) * cs.om;
+    }
+    const T cf = cs.cf;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) cs.sig[a][b] = T(0);
     if constexpr (WITH_SIGMA) {
@@ -502,8 +525,18 @@ hipError_t launch_totals(int lat, int storage, const void *A, double *partials, 
                          const GridDims &gd, const StepCoef &co, hipStream_t stream);
 hipError_t launch_convert(int storage, const double *src, void *dst, int64_t n,
                           hipStream_t stream);
-hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const TileSim *table, int nsims,
-                             int64_t ntiles, int parity, int blocks, hipStream_t stream);
+// One launch of the multi-grid step: tile list, its members, launch shape.
+struct BatchLaunch {
+    const int64_t *begin;   // device: first tile of member k (k < nsims), ascending
+    const TileSim *table;   // device: the members
+    int nsims;
+    int64_t ntiles;         // tiles of all members
+    int parity;             // batch steps since the table was built, mod 2
+    int threads;            // tile width = threads per block (64, 128 or 256)
+    int64_t blocks;         // 0: one block per tile; > 0: persistent walk
+    hipStream_t stream;
+};
+hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl);
 
 // Per-lattice / per-storage pieces, each explicitly instantiated in its own
 // translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
@@ -511,8 +544,7 @@ template <int LAT, class S>
 hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                           const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
 template <int LAT, class S>
-hipError_t launch_multi_step_ls(int eq, int fo, const TileSim *table, int nsims, int64_t ntiles,
-                                int parity, int blocks, hipStream_t stream);
+hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl);
 template <int LAT>
 hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
                          const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,

@@ -71,14 +71,14 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
         ys[d] = wrap3(y - (d - 3), gd.ny);
         zs[d] = (L::D == 3) ? wrap3(z - (d - 3), gd.nz) : 0;
     }
-    const int64_t N = gd.N;
-    const uint32_t plane_bytes = uint32_t(N * int64_t(sizeof(S)));
+    const int64_t P = gd.P;
+    const uint32_t plane_bytes = uint32_t(P * int64_t(sizeof(S)));
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
         const uint32_t row =
-            uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx) * uint32_t(sizeof(S));
-        const auto r = plane_rsrc(A + int64_t(i) * N, plane_bytes);
+            uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px) * uint32_t(sizeof(S));
+        const auto r = plane_rsrc(A + int64_t(i) * P, plane_bytes);
         h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
     });
 }
@@ -102,9 +102,10 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
 {
     using L = Lattice<LAT>;
     using T = typename ArithOf<S>::type;
-    const int64_t N = gd.N;
-    const int64_t rowbase = (int64_t(z) * gd.ny + y) * gd.nx;  // uniform
-    const int64_t cell = rowbase + x;
+    const int64_t P = gd.P;
+    const int64_t row = int64_t(z) * gd.ny + y;  // uniform
+    const int64_t rowbase = row * gd.px;          // padded population row
+    const int64_t cell = row * gd.nx + x;         // dense field index
     // one population plane is < 4 GiB (checked at creation), so 32-bit byte
     // offsets address it
 
@@ -115,28 +116,28 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
 
     const RawSums<T> rs = raw_sums<L, T>(h);
     CellState<T> cs;
-    finish_moments<L, T, FO == 4>(rs, g, T(co.cf), T(co.rho0), cs);
+    finish_moments<L, T, FO == 4>(rs, g, co, cs);
 
     // h* = h + om (f0 - f) + cf F with f0 - f = w drho + (f0 - w rho) - h:
     //    = h + fma(om, fma(w, drho, -h), [om (f0 - w rho) + cf F]).
     // The bracket is what combo_pairs returns with NO_BASE (even +- odd part);
     // every term is a small deviation, so the rounding stays at the size of h.
-    const T om = T(co.om);
+    const T om = cs.om;
     const T drho = cs.drho;
     const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
     const uint32_t ro = uint32_t(rowbase) * uint32_t(sizeof(S));
-    const uint32_t plane_bytes = uint32_t(N * int64_t(sizeof(S)));
-    combo_pairs<L, T, EQ, FO, true>(cs, om, T(co.cf), [&](auto IP, auto IM, T ev, T od) {
+    const uint32_t plane_bytes = uint32_t(P * int64_t(sizeof(S)));
+    combo_pairs<L, T, EQ, FO, true>(cs, om, cs.cf, [&](auto IP, auto IM, T ev, T od) {
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip));
         const T dp = fma_t(T(w), drho, -h[ip]);
         BufIO<S>::store(Codec<L, S>::template store<ip, T>(h[ip] + fma_t(om, dp, ev + od)),
-                        plane_rsrc(B + int64_t(ip) * N, plane_bytes), xo, ro);
+                        plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
         if constexpr (im >= 0) {
             const T dm = fma_t(T(w), drho, -h[im]);
             BufIO<S>::store(Codec<L, S>::template store<im, T>(h[im] + fma_t(om, dm, ev - od)),
-                            plane_rsrc(B + int64_t(im) * N, plane_bytes), xo, ro);
+                            plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
         }
     });
 }
@@ -154,35 +155,41 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
 }
 
 // ---------------------------------------------------------------------------
-// K1b: persistent multi-grid step.  Several simulations (same lattice, storage
-// and orders; any grid sizes, relaxation times and forces) advance one step in
-// one launch.  The work is a list of tiles -- one tile is one grid row (all x)
-// of one simulation -- and each block walks the list with a fixed stride, so
-// every block exits after at most ceil(ntiles / gridDim.x) tiles and the
-// tile -> block assignment (hence every result) does not depend on timing.
+// K1b: multi-grid step.  Several simulations (same lattice, storage and
+// orders; any grid sizes, relaxation times and forces) advance one step in one
+// launch.  The work is a list of tiles -- one tile is a run of blockDim.x cells
+// along x of one grid row of one simulation -- and block b takes tiles b,
+// b + gridDim.x, ...: with one block per tile the hardware balances uneven
+// members; with fewer blocks the grid is persistent and every block exits
+// after at most ceil(ntiles / gridDim.x) tiles.  Each cell is updated by
+// exactly one thread with the arithmetic of the single-grid step, so no
+// result depends on the launch shape or on the other members.
 // ---------------------------------------------------------------------------
 template <int LAT, class S, int EQ, int FO>
-__global__ void __launch_bounds__(256) multi_step_kernel(const TileSim *__restrict__ sims,
-                                                          int nsims, int64_t ntiles, int parity)
+__global__ void __launch_bounds__(256)
+    multi_step_kernel(const int64_t *__restrict__ begin, const TileSim *__restrict__ sims,
+                      int nsims, int64_t ntiles, int parity)
 {
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        // the simulation owning tile t: last s with tile_begin <= t (uniform)
+        // the simulation owning tile t: last k with begin[k] <= t (uniform)
         int lo = 0, hi = nsims - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (sims[mid].tile_begin <= t) lo = mid;
+            if (begin[mid] <= t) lo = mid;
             else hi = mid - 1;
         }
         const TileSim &sd = sims[lo];
-        const uint32_t row = uint32_t(t - sd.tile_begin);  // ny * nz < 2^32
+        // tiles of one simulation number fewer than its cells (< 2^32)
+        const uint32_t k = uint32_t(t - begin[lo]);
+        const uint32_t cx = uint32_t(sd.chunks_x);
+        const uint32_t row = k / cx;
+        const uint32_t xc = k - row * cx;
         const int y = int(row % uint32_t(sd.gd.ny)), z = int(row / uint32_t(sd.gd.ny));
+        const int x = int(xc * blockDim.x + threadIdx.x);
         const int c = sd.cur ^ parity;
         const S *A = static_cast<const S *>(sd.pop[c]);
         S *B = static_cast<S *>(const_cast<void *>(sd.pop[c ^ 1]));
-        for (int x0 = 0; x0 < sd.gd.nx; x0 += int(blockDim.x)) {
-            const int x = x0 + int(threadIdx.x);
-            if (x < sd.gd.nx) step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
-        }
+        if (x < sd.gd.nx) step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
     }
 }
 
@@ -221,7 +228,7 @@ __device__ __forceinline__ void gather_any(const void *A, int storage, const Gri
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
         const int64_t idx =
-            int64_t(i) * gd.N + (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.nx + xs[cx + 3];
+            int64_t(i) * gd.P + (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px + xs[cx + 3];
         h[i] = load_any<L, i>(A, storage, idx);
     });
 }
@@ -279,8 +286,8 @@ __global__ void __launch_bounds__(256)
             const int xd = wrap3(x - L::c(i, 0), gd.nx);
             const int yd = wrap3(y - L::c(i, 1), gd.ny);
             const int zd = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
-            const int64_t dst = (int64_t(zd) * gd.ny + yd) * gd.nx + xd;
-            store_any<L, i>(A, storage, int64_t(i) * N + dst, v);
+            const int64_t dst = (int64_t(zd) * gd.ny + yd) * gd.px + xd;
+            store_any<L, i>(A, storage, int64_t(i) * gd.P + dst, v);
         };
         const double base = w * cs.drho;
         put(std::integral_constant<int, ip>{}, base + (ev + od));
@@ -309,7 +316,7 @@ __global__ void __launch_bounds__(256)
     force_any(fd, storage, gd, L::D, x, y, z, cell, g);
     const RawSums<double> rs = raw_sums<L, double>(h);
     CellState<double> cs;
-    finish_moments<L, double, false>(rs, g, co.cf, co.rho0, cs);
+    finish_moments<L, double, false>(rs, g, co, cs);
     if (rho) rho[cell] = cs.rho;
     if (theta) theta[cell] = cs.th;
     if (u)
@@ -338,8 +345,8 @@ __global__ void __launch_bounds__(256)
     force_any(fd, storage, gd, L::D, x, y, z, cell, g);
     const RawSums<double> rs = raw_sums<L, double>(h);
     CellState<double> cs;
-    finish_moments<L, double, FO == 4>(rs, g, co.cf, co.rho0, cs);
-    const double cf = co.cf;
+    finish_moments<L, double, FO == 4>(rs, g, co, cs);
+    const double cf = cs.cf;
     double qa[3] = {0.0, 0.0, 0.0};
     auto acc = [&](auto II, double fp) {
         constexpr int i = decltype(II)::value;
@@ -388,15 +395,17 @@ __global__ void __launch_bounds__(256)
 {
     using L = Lattice<LAT>;
     __shared__ double lds[4];
-    const int64_t N = gd.N;
-    const int64_t chunk = (N + TOTALS_BLOCKS - 1) / TOTALS_BLOCKS;
+    // block b sums a fixed run of grid rows (the padding of each row is skipped)
+    const int64_t rows = int64_t(gd.ny) * gd.nz;
+    const int64_t chunk = (rows + TOTALS_BLOCKS - 1) / TOTALS_BLOCKS;
     const int64_t lo = int64_t(blockIdx.x) * chunk;
-    const int64_t hi = (lo + chunk < N) ? lo + chunk : N;
+    const int64_t hi = (lo + chunk < rows) ? lo + chunk : rows;
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         double v = 0.0;
-        for (int64_t k = lo + threadIdx.x; k < hi; k += 256)
-            v += load_any<L, i>(A, storage, int64_t(i) * N + k);
+        for (int64_t r = lo; r < hi; ++r)
+            for (int x = threadIdx.x; x < gd.nx; x += 256)
+                v += load_any<L, i>(A, storage, int64_t(i) * gd.P + r * gd.px + x);
         v = block_sum_256(v, lds);
         if (threadIdx.x == 0) partials[int64_t(blockIdx.x) * L::Q + i] = v;
     });

@@ -2,6 +2,8 @@
 // instantiate them explicitly.
 #pragma once
 
+#include <algorithm>
+
 #include "lbm_kernels.h"
 
 namespace lbm {
@@ -46,13 +48,17 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
 }
 
 template <int LAT, class S>
-hipError_t launch_multi_step_ls(int eq, int fo, const TileSim *table, int nsims, int64_t ntiles,
-                                int parity, int blocks, hipStream_t stream)
+hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl)
 {
+    if (bl.ntiles <= 0) return hipSuccess;
+    // one block per tile, or the persistent grid; the kernel strides over the
+    // list, so a grid capped at 2^31 - 1 blocks still covers every tile
+    int64_t grid = bl.blocks > 0 ? std::min(bl.blocks, bl.ntiles) : bl.ntiles;
+    grid = std::min<int64_t>(grid, 0x7fffffff);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((multi_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
-                           dim3(unsigned(blocks)), dim3(256), 0, stream, table, nsims, ntiles,
-                           parity);
+                           dim3(unsigned(grid)), dim3(unsigned(bl.threads)), 0, bl.stream,
+                           bl.begin, bl.table, bl.nsims, bl.ntiles, bl.parity);
         return hipGetLastError();
     });
 }

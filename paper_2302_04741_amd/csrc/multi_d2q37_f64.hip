@@ -2,6 +2,5 @@
 #include "lbm_launch.h"
 
 namespace lbm {
-template hipError_t launch_multi_step_ls<0, double>(int, int, const TileSim *, int, int64_t, int,
-                                                     int, hipStream_t);
+template hipError_t launch_multi_step_ls<0, double>(int, int, const BatchLaunch &);
 }  // namespace lbm

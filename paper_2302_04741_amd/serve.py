@@ -117,12 +117,13 @@ class Server:
     def __init__(self, storage: str = "f32", max_slots: int = 64,
                  budget_bytes: int = 16 << 30, chunk_steps: int = 100,
                  keep_populations: Callable[[int], bool] = lambda rid: False,
-                 batch_blocks: int = 0, check_every: int = 5):
+                 batch_threads: int = 0, batch_blocks: int = 0, check_every: int = 5):
         self.storage = storage
         self.check_every = max(1, int(check_every))
         self.adm = Admission(max_slots, budget_bytes)
         self.chunk = int(chunk_steps)
         self.keep = keep_populations
+        self.batch_threads = batch_threads
         self.batch_blocks = batch_blocks
 
     def run(self, requests: List[Request], realtime: bool = True) -> Dict[str, object]:
@@ -140,8 +141,8 @@ class Server:
         active = []   # dicts: req, sim, bytes, admitted, done
         results: List[Result] = []
         batch = sim.Batch(self.adm.max_slots)
-        if self.batch_blocks:
-            batch.set_blocks(self.batch_blocks)
+        if self.batch_threads or self.batch_blocks:
+            batch.set_launch(self.batch_threads, self.batch_blocks)
         members = None
         t0 = time.perf_counter()
         lu = 0

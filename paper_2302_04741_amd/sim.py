@@ -193,6 +193,11 @@ class Sim:
     def step_count(self, n: int):
         check(load().lbm_set_step_count(self.handle, int(n)))
 
+    def set_viscosity(self, mu: float):
+        """mu > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (the
+        dynamic viscosity held constant); 0: the constant tau_hat again."""
+        check(load().lbm_set_viscosity(self.handle, float(mu)))
+
     def set_block(self, threads: int):
         check(load().lbm_set_block(self.handle, int(threads)))
 
@@ -207,6 +212,8 @@ def from_workload(wl, storage="f64", **kw) -> Sim:
     s = Sim(wl.lattice, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, storage=storage,
             eq_order=wl.eq_order, force_order=wl.force_order, force_field=force_field, **kw)
     s.set_workload_force(wl.force)
+    if wl.mu > 0:
+        s.set_viscosity(wl.mu)
     return s
 
 
@@ -240,9 +247,9 @@ class Graph:
 
 
 class Batch:
-    """Several Sims advanced together by the persistent multi-grid kernel: one
-    launch per step for all members (same lattice, storage and orders; any grid
-    sizes, relaxation times and forces)."""
+    """Several Sims advanced together by the multi-grid kernel: one launch per
+    step for all members (same lattice, storage and orders; any grid sizes,
+    relaxation times and forces)."""
 
     def __init__(self, max_sims: int, device=None, stream=None):
         torch = _torch()
@@ -275,8 +282,10 @@ class Batch:
     def step(self, n: int = 1):
         check(load().lbm_batch_step(self.handle, int(n)))
 
-    def set_blocks(self, blocks: int):
-        check(load().lbm_batch_set_blocks(self.handle, int(blocks)))
+    def set_launch(self, threads: int = 0, blocks: int = 0):
+        """Tile width / threads per block (64, 128, 256; 0 = 256) and grid
+        (0 = one block per tile, > 0 = persistent grid of that many blocks)."""
+        check(load().lbm_batch_set_launch(self.handle, int(threads), int(blocks)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

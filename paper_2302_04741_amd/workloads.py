@@ -50,6 +50,7 @@ class Workload:
     steps: int
     eq_order: int = 0
     force_order: int = 4
+    mu: float = 0.0  # > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2
 
     @property
     def D(self) -> int:

@@ -29,7 +29,8 @@ def gpu_moments(sim):
 def oracle_run(oracle_mod, wl, steps, nthreads=0, prec="f64"):
     sim = oracle_mod.OracleSim(LAT_ID[wl.lattice], wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta,
                                wl.force_field(), eq_order=wl.eq_order,
-                               force_order=wl.force_order, nthreads=nthreads, prec=prec)
+                               force_order=wl.force_order, nthreads=nthreads, prec=prec,
+                               mu=wl.mu)
     sim.step(steps)
     return sim
 
@@ -60,7 +61,7 @@ def oracle_window_moments(oracle_mod, wl, center, steps, g_field=None):
     sim = oracle_mod.OracleSim(LAT_ID[wl.lattice], wdims, wl.tau_hat, wl.rho[idx],
                                np.ascontiguousarray(wl.u[:, idx]), wl.theta[idx],
                                np.ascontiguousarray(g[:, idx]), eq_order=wl.eq_order,
-                               force_order=wl.force_order)
+                               force_order=wl.force_order, mu=wl.mu)
     sim.step(steps)
     r, u, t = sim.moments()
     mid = len(idx) // 2

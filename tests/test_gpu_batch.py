@@ -38,6 +38,8 @@ def mix(lattice, storage, seed=0):
         kind = ["uniform", "axis", "field"][k % 3]
         wl = workloads.random_smooth(lattice, dims, seed=seed * 100 + k, force_kind=kind,
                                      g_amp=1e-3, tau_hat=float(rng.uniform(0.6, 1.0)))
+        if k == 1:
+            wl.mu = 0.15  # one member with the per-cell relaxation time
         wls.append(wl)
     return wls
 
@@ -62,6 +64,39 @@ def test_batch_member_independent_of_mix_bitwise(sim_mod, lattice, storage):
     b.step(7)  # odd counts: the buffer parity is carried between calls
     for s, ref in zip(sims, alone):
         assert s.step_count == 13
+        assert torch.equal(s.get_populations().cpu(), ref)
+
+
+# (threads = tile width, blocks: 0 = one block per tile, else a persistent grid)
+LAUNCHES = [(256, 0), (64, 0), (128, 0), (256, 3), (64, 1000)]
+
+
+@pytest.mark.parametrize("lattice,storage", [("D2Q37", "f32"), ("D3Q39", "f64")])
+def test_batch_launch_shapes_bitwise(sim_mod, lattice, storage):
+    wls = mix(lattice, storage, seed=4)
+    out = []
+    for threads, blocks in LAUNCHES:
+        sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
+        b = sim_mod.Batch(len(sims))
+        b.set_launch(threads, blocks)
+        b.set(sims)
+        b.step(7)
+        out.append([s.get_populations().cpu() for s in sims])
+        b.close()
+        for s in sims:
+            s.close()
+    for k in range(1, len(LAUNCHES)):
+        for a, c in zip(out[0], out[k]):
+            assert torch.equal(a, c), LAUNCHES[k]
+    # a new tile width between steps rebuilds the table from the current state
+    sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
+    b = sim_mod.Batch(len(sims))
+    b.set(sims)
+    b.step(3)
+    b.set_launch(64, 0)
+    b.step(4)
+    for s, ref in zip(sims, out[0]):
+        assert s.step_count == 7
         assert torch.equal(s.get_populations().cpu(), ref)
 
 
@@ -158,4 +193,9 @@ def test_batch_graph_replays(sim_mod):
             torch.cuda.synchronize()
             for s, r in zip(sims, refs):
                 assert torch.equal(s.get_populations(), r.get_populations())
+        from paper_2302_04741_amd._lib import LbmError
+
+        b.set_launch(128, 0)  # a new launch shape makes the captured graph stale
+        with pytest.raises(LbmError):
+            g.launch(1)
     torch.cuda.synchronize()

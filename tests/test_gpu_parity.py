@@ -198,3 +198,58 @@ def test_set_force_before_first_step_rebuilds_state(sim_mod, oracle_mod):
     s.step(15)
     ora = oracle_run(oracle_mod, wl, 15).moments()
     assert max(rel_err(gpu_moments(s), ora)) < TOL64
+
+
+# Per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (Sec. 3: constant dynamic
+# viscosity), on fields with +-15% temperature and +-5% density variation, so
+# tau^ differs from cell to cell by ~20%.  Same bars as the constant-tau runs.
+def viscous_workload(lat, dims, seed=31, fo=4):
+    wl = workloads.random_smooth(lat, dims, seed=seed, force_kind="axis", g_amp=1e-3,
+                                 amp_theta=0.15, amp_rho=0.05, force_order=fo)
+    wl.mu = 0.2
+    return wl
+
+
+@pytest.mark.parametrize("lat,dims,rho0,prec", [("D2Q37", (64, 64, 1), 0.0, "f64"),
+                                                ("D2Q37", (41, 33, 1), 1.0, "ld"),
+                                                ("D3Q39", (12, 10, 14), 1.0, "f64")])
+def test_parity_viscosity_mode(sim_mod, oracle_mod, lat, dims, rho0, prec):
+    check_parity(sim_mod, oracle_mod, viscous_workload(lat, dims), 200, rho0=rho0, prec=prec)
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q37", (70, 9, 1)), ("D3Q39", (9, 7, 66))])
+def test_parity_viscosity_mode_fp32(sim_mod, oracle_mod, lat, dims):
+    check_parity(sim_mod, oracle_mod, viscous_workload(lat, dims), 25, tol=TOL32_SHORT,
+                 storage="f32")
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q37", (16, 12, 1)), ("D3Q39", (6, 5, 7))])
+def test_heat_flux_parity_viscosity_mode(sim_mod, oracle_mod, lat, dims):
+    wl = viscous_workload(lat, dims, seed=22)
+    s = sim_mod.from_workload(wl)
+    s.step(20)
+    q = to_host(s.heat_flux())
+    qo = oracle_run(oracle_mod, wl, 20).heat_flux()
+    err = np.abs(q - qo).max() / np.abs(qo).max()
+    print("heat flux, per-cell tau", lat, err, flush=True)
+    assert err < 1e-11
+
+
+def test_viscosity_mode_can_be_switched_off(sim_mod, oracle_mod):
+    wl = viscous_workload("D2Q37", (20, 18, 1), seed=5)
+    s = sim_mod.from_workload(wl)
+    s.step(10)
+    s.set_viscosity(0.0)  # back to the constant tau_hat of the parameters
+    s.step(10)
+    ora = oracle_mod.OracleSim(LAT_ID[wl.lattice], wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta,
+                               wl.force_field(), mu=wl.mu)
+    ora.step(10)
+    ora.mu = 0.0
+    ora.step(10)
+    assert max(rel_err(gpu_moments(s), ora.moments())) < TOL64
+    from paper_2302_04741_amd._lib import LbmError
+
+    with pytest.raises(LbmError):
+        s.set_viscosity(-1.0)
+    with pytest.raises(LbmError):
+        s.set_viscosity(float("nan"))

@@ -128,6 +128,8 @@ def test_workspace_and_field_checks(lib):
     ("D2Q37", (1024, 1024, 1), "f32", 4, 37, 2),
     ("D3Q39", (256, 256, 256), "f32", 4, 39, 3),
     ("D3Q39", (32, 32, 32), "f64", 8, 39, 3),
+    ("D2Q37", (1017, 33, 1), "f32", 4, 37, 2),
+    ("D3Q39", (5, 7, 3), "f16dev", 2, 39, 3),
 ])
 def test_workspace_size(lattice, dims, storage, sbytes, Q, D):
     def up(v):
@@ -135,11 +137,13 @@ def test_workspace_size(lattice, dims, storage, sbytes, Q, D):
 
     p = _lib.make_params(lattice, dims, 0.8, storage)
     N = int(np.prod(dims))
+    # population rows are padded to a multiple of 64 values
+    P = (dims[0] + 63) // 64 * 64 * dims[1] * dims[2]
     abytes = 8 if storage == "f64" else 4
-    expect = 2 * up(Q * N * sbytes) + up(D * max(dims) * abytes) + up(512 * Q * 8) + up(64)
+    expect = 2 * up(Q * P * sbytes) + up(D * max(dims) * abytes) + up(512 * Q * 8) + up(64)
     assert _lib.workspace_bytes(p) == expect
     pf = _lib.make_params(lattice, dims, 0.8, storage, force_field=True)
-    expect_f = 2 * up(Q * N * sbytes) + up(D * N * abytes) + up(512 * Q * 8) + up(64)
+    expect_f = 2 * up(Q * P * sbytes) + up(D * N * abytes) + up(512 * Q * 8) + up(64)
     assert _lib.workspace_bytes(pf) == expect_f
 
 
@@ -155,6 +159,7 @@ def test_null_handle_calls(lib):
     assert lib.lbm_set_step_count(None, 0) == _lib.LBM_EINVAL
     assert lib.lbm_set_block(None, 64) == _lib.LBM_EINVAL
     assert lib.lbm_set_stream(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_set_viscosity(None, 0.1) == _lib.LBM_EINVAL
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_population_bytes(None) == 0
     assert lib.lbm_lattice_table(5, None, None, None) == _lib.LBM_EINVAL
@@ -210,7 +215,13 @@ def test_batch_and_graph_argument_checks(lib):
     arr = (ctypes.c_void_p * 1)(None)
     assert lib.lbm_batch_set(h, arr, 1) == _lib.LBM_EINVAL  # NULL member
     assert lib.lbm_batch_set(h, arr, 5) == _lib.LBM_EINVAL  # more than max_sims
-    assert lib.lbm_batch_set_blocks(h, -1) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_set_launch(h, 0, -1) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_set_launch(h, 100, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_set_launch(h, 512, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_batch_set_launch(h, 0, 1 << 31) == _lib.LBM_EINVAL
+    for threads in (0, 64, 128, 256):  # no members yet: nothing to rebuild
+        assert lib.lbm_batch_set_launch(h, threads, 1024) == _lib.LBM_OK
+    assert lib.lbm_batch_set_launch(None, 0, 0) == _lib.LBM_EINVAL
     g = ctypes.c_void_p()
     assert lib.lbm_graph_create(None, None, 2, ctypes.byref(g)) == _lib.LBM_EINVAL
     assert lib.lbm_graph_create(None, h, 2, ctypes.byref(g)) == _lib.LBM_EINVAL  # no members
