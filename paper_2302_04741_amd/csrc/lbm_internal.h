@@ -46,8 +46,11 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 // work, and the hardware range check drops accesses past the plane.
 // ---------------------------------------------------------------------------
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer, 32-bit data format
-// Cache policy of the step's population traffic: non-temporal (every element is
-// read once and written once per step; measured ~4% faster than the default).
+// Cache policy of the step's population traffic.  Every element is read once
+// and written once per step.  Stores are non-temporal (6% faster than default
+// stores on the D3Q39 FP32 step); loads keep the default policy (1.3% / 1.8% /
+// 4.5% faster than non-temporal loads for FP32 / FP64 / F16 storage).
+constexpr int BUF_LD = 0;
 constexpr int BUF_NT = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t bytes)
@@ -61,7 +64,7 @@ template <> struct BufIO<float> {
     __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
     {
         return __builtin_bit_cast(float,
-                                  __builtin_amdgcn_raw_buffer_load_b32(r, int(v), int(s), BUF_NT));
+                                  __builtin_amdgcn_raw_buffer_load_b32(r, int(v), int(s), BUF_LD));
     }
     __device__ static __forceinline__ void store(float x, __amdgpu_buffer_rsrc_t r, uint32_t v,
                                                  uint32_t s)
@@ -74,7 +77,7 @@ template <> struct BufIO<double> {
     __device__ static __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
     {
         return __builtin_bit_cast(double,
-                                  __builtin_amdgcn_raw_buffer_load_b64(r, int(v), int(s), BUF_NT));
+                                  __builtin_amdgcn_raw_buffer_load_b64(r, int(v), int(s), BUF_LD));
     }
     __device__ static __forceinline__ void store(double x, __amdgpu_buffer_rsrc_t r, uint32_t v,
                                                  uint32_t s)
@@ -87,7 +90,7 @@ template <> struct BufIO<__half> {
     __device__ static __forceinline__ __half load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s)
     {
         return __builtin_bit_cast(__half,
-                                  __builtin_amdgcn_raw_buffer_load_b16(r, int(v), int(s), BUF_NT));
+                                  __builtin_amdgcn_raw_buffer_load_b16(r, int(v), int(s), BUF_LD));
     }
     __device__ static __forceinline__ void store(__half x, __amdgpu_buffer_rsrc_t r, uint32_t v,
                                                  uint32_t s)
