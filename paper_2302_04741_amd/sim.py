@@ -30,9 +30,9 @@ def _as_device(torch, a, shape, device, stream, keep):
     else:
         arr = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape))
         t = torch.from_numpy(arr.copy()).to(device=device, non_blocking=False)
-    if t.data_ptr() != getattr(a, "data_ptr", lambda: None)():
-        # a temporary owned here: keep it alive until the stream has used it
-        t.record_stream(stream)
+    # read on `stream`: keep the memory from being reused before that stream
+    # has used it (the caller's tensor itself, or a temporary made here)
+    t.record_stream(stream)
     keep.append(t)
     return t
 
@@ -78,6 +78,7 @@ class Sim:
         self._ws_ptr = raw.data_ptr() + off
         keep = []
         N, D = self.N, self.D
+        self._before()  # inputs made on the caller's stream are ready first
         with torch.cuda.stream(self.stream):
             r = _as_device(torch, rho, (N,), self.device, self.stream, keep)
             uu = _as_device(torch, u, (D, N), self.device, self.stream, keep)
@@ -101,6 +102,24 @@ class Sim:
         torch = _torch()
         return torch.empty(shape, dtype=torch.float64, device=self.device)
 
+    # Stream ordering.  The library runs everything on the handle's stream;
+    # tensors handed in or out belong to the caller's current stream.  Before
+    # the handle's stream touches such tensors it waits for the current
+    # stream; after it wrote them the current stream waits for it, and the
+    # allocator is told the tensors were used on the handle's stream.
+    def _before(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _after(self, cur, *tensors):
+        if cur.cuda_stream != self.stream.cuda_stream:
+            for t in tensors:
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+
     # -- the five calls ------------------------------------------------------
     def set_force(self, g=None, *, axis=None, profile=None, field=None):
         """Uniform g (D values), an axis profile (D, L_axis) along `axis`, or a
@@ -112,6 +131,7 @@ class Sim:
             check(L.lbm_set_force(self.handle, 0, gg, 0, 0))
             return
         keep = []
+        self._before()
         with torch.cuda.stream(self.stream):
             self._set_force_device(torch, L, keep, axis, profile, field)
 
@@ -144,10 +164,13 @@ class Sim:
         check(load().lbm_step(self.handle, int(n)))
 
     def moments(self):
-        """(rho (N,), u (D, N), theta (N,)) as float64 device tensors."""
+        """(rho (N,), u (D, N), theta (N,)) as float64 device tensors, ready on
+        the caller's current stream."""
         rho, u, th = self._empty(self.N), self._empty(self.D, self.N), self._empty(self.N)
+        cur = self._before()
         check(load().lbm_moments(self.handle, ctypes.c_void_p(rho.data_ptr()),
                                  ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(th.data_ptr())))
+        self._after(cur, rho, u, th)
         return rho, u, th
 
     def close(self):
@@ -164,7 +187,9 @@ class Sim:
     # -- diagnostics -----------------------------------------------------------
     def heat_flux(self):
         q = self._empty(self.D, self.N)
+        cur = self._before()
         check(load().lbm_heat_flux(self.handle, ctypes.c_void_p(q.data_ptr())))
+        self._after(cur, q)
         return q
 
     def totals(self) -> np.ndarray:
@@ -178,12 +203,17 @@ class Sim:
     def get_populations(self):
         torch = _torch()
         t = torch.empty(self.population_bytes(), dtype=torch.uint8, device=self.device)
+        cur = self._before()
         check(load().lbm_get_populations(self.handle, ctypes.c_void_p(t.data_ptr())))
+        self._after(cur, t)
         return t
 
     def set_populations(self, t):
         assert t.numel() * t.element_size() == self.population_bytes()
+        assert t.is_contiguous() and t.device.type == "cuda"
+        cur = self._before()
         check(load().lbm_set_populations(self.handle, ctypes.c_void_p(t.data_ptr())))
+        self._after(cur, t)
 
     @property
     def step_count(self) -> int:
@@ -232,7 +262,11 @@ class Graph:
         self.target = target
 
     def launch(self, repeats: int = 1):
+        if isinstance(self.target, Batch):
+            self.target._pre()
         check(load().lbm_graph_launch(self._h, int(repeats)))
+        if isinstance(self.target, Batch):
+            self.target._post()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -267,6 +301,7 @@ class Batch:
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.members = []
+        self._member_streams = {}
 
     @property
     def handle(self):
@@ -274,13 +309,29 @@ class Batch:
             raise RuntimeError("batch is closed")
         return self._h
 
+    def _pre(self):
+        for st in self._member_streams.values():
+            self.stream.wait_stream(st)
+
+    def _post(self):
+        for st in self._member_streams.values():
+            st.wait_stream(self.stream)
+
     def set(self, sims):
         arr = (ctypes.c_void_p * len(sims))(*[s.handle.value for s in sims])
         check(load().lbm_batch_set(self.handle, arr, len(sims)))
         self.members = list(sims)
+        self._member_streams = {}
+        for s in sims:
+            if s.stream.cuda_stream != self.stream.cuda_stream:
+                self._member_streams[s.stream.cuda_stream] = s.stream
 
     def step(self, n: int = 1):
+        # members may run their own work on other streams: order the batch's
+        # launches after it, and their later work after the batch
+        self._pre()
         check(load().lbm_batch_step(self.handle, int(n)))
+        self._post()
 
     def set_launch(self, threads: int = 0, blocks: int = 0):
         """Tile width / threads per block (64, 128, 256; 0 = 256) and grid
