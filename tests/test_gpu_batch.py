@@ -199,3 +199,32 @@ def test_batch_graph_replays(sim_mod):
         with pytest.raises(LbmError):
             g.launch(1)
     torch.cuda.synchronize()
+
+
+def test_autotuner_picks_and_caches_launch_shapes(sim_mod, tmp_path, monkeypatch):
+    from paper_2302_04741_amd import autotune
+
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    b = autotune.tune_block("D3Q39", (64, 48, 40), storage="f32", steps=4)
+    assert b in autotune.BLOCK_CANDIDATES
+    dims_list = [(100, 37, 1), (64, 64, 1), (257, 9, 1)]
+    launch = autotune.tune_batch_launch("D2Q37", dims_list, storage="f32", steps=4)
+    assert launch in autotune.BATCH_CANDIDATES
+    import json
+
+    cache = json.loads((tmp_path / "tune.json").read_text())
+    assert len(cache) == 2 and all("ms_per_step" in v for v in cache.values())
+    # a second call is served from the cache (no timing run)
+    assert autotune.tune_batch_launch("D2Q37", dims_list, storage="f32") == launch
+    # the tuned shape gives the same populations as the default shape
+    wls = [workloads.random_smooth("D2Q37", d, seed=k) for k, d in enumerate(dims_list)]
+    out = []
+    for shape in (None, launch):
+        sims = [sim_mod.from_workload(wl, storage="f32") for wl in wls]
+        bt = sim_mod.Batch(len(sims))
+        if shape:
+            bt.set_launch(*shape)
+        bt.set(sims)
+        bt.step(5)
+        out.append([s.get_populations().cpu() for s in sims])
+    assert all(torch.equal(a, c) for a, c in zip(*out))
