@@ -78,9 +78,9 @@ def lib(prec: str = "f64"):
         L.oracle_maxwell_coeff.argtypes = [_int, _int, R, _ptr, R, _ptr]
         L.oracle_equilibrium.argtypes = [_int, _int, R, _ptr, R, _ptr]
         L.oracle_force.argtypes = [_int, _int, R, _ptr, R, _ptr, _ptr, _ptr]
-        L.oracle_init.argtypes = [_int, _i64, _i64, _i64, _int, _int,
+        L.oracle_init.argtypes = [_int, _i64, _i64, _i64, _int, _int, _ptr,
                                   _ptr, _ptr, _ptr, _ptr, _ptr, _int]
-        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, R, R, _int, _int,
+        L.oracle_step.argtypes = [_int, _i64, _i64, _i64, R, R, _int, _int, _ptr,
                                   _ptr, _ptr, _ptr, _i64, _int]
         L.oracle_moments.argtypes = [_int, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _int]
         L.oracle_sigma.argtypes = [_int, _i64, R, R, _int, _ptr, _ptr, _ptr, _int]
@@ -192,7 +192,7 @@ class OracleSim:
 
     def __init__(self, lat: int, dims, tau_hat: float, rho, u, theta, g,
                  eq_order: int = 0, force_order: int = 4, nthreads: int = 0,
-                 prec: str = "f64", mu: float = 0.0):
+                 prec: str = "f64", mu: float = 0.0, walls=None):
         self.lat = lat
         self.D = DIM[lat]
         self.prec = prec
@@ -205,6 +205,10 @@ class OracleSim:
         self.tau_hat = float(tau_hat)
         # mu > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (Sec. 3)
         self.mu = float(mu)
+        # walls: None (periodic) or (theta_b, theta_t, U_b, U_t): plates normal to
+        # y at y = -1/2 and y = ny - 1/2 (Sec. 3 channel; the wall condition is
+        # described in lbm_oracle.c)
+        self.walls = None if walls is None else np.asarray(walls, dtype=_DTYPE[prec]).copy()
         self.eq_order = eq_order
         self.force_order = force_order
         self.nthreads = nthreads
@@ -215,8 +219,9 @@ class OracleSim:
         self.set_force(g)
         self.f = np.zeros((N, self.Q), dtype=dt)
         self._tmp = np.zeros_like(self.f)
-        _check(self.L.oracle_init(lat, *self.dims, eq_order, force_order, _p(rho), _p(u),
-                                  _p(theta), _p(self.g), _p(self.f), nthreads), "init")
+        _check(self.L.oracle_init(lat, *self.dims, eq_order, force_order, self._walls_p(),
+                                  _p(rho), _p(u), _p(theta), _p(self.g), _p(self.f), nthreads),
+               "init")
         self.time = 0
 
     def set_force(self, g):
@@ -225,10 +230,13 @@ class OracleSim:
             g = g_uniform(self.D, self.N, g)
         self.g = np.ascontiguousarray(g.reshape(self.D, self.N).astype(self.dt))
 
+    def _walls_p(self):
+        return None if self.walls is None else _p(self.walls)
+
     def step(self, n: int = 1):
         _check(self.L.oracle_step(self.lat, *self.dims, self.tau_hat, self.mu, self.eq_order,
-                                  self.force_order, _p(self.g), _p(self.f), _p(self._tmp),
-                                  int(n), self.nthreads), "step")
+                                  self.force_order, self._walls_p(), _p(self.g), _p(self.f),
+                                  _p(self._tmp), int(n), self.nthreads), "step")
         self.time += int(n)
 
     def moments(self):

@@ -33,6 +33,11 @@
  *                                viscosity and the conductivity constant; with
  *                                tau^ = tau + 1/2 and the cell's mid-point rho and
  *                                theta of the same step (mu > 0 selects it).
+ *   walls ...................... Sec. 3 runs its channel between two plates with a
+ *                                multi-speed mass-conserving wall condition it does
+ *                                not publish; the one here is this project's own
+ *                                (diffuse reflection, mass balanced per column),
+ *                                described at or_walls below.
  *
  * Readings where the paper is silent or garbled (all documented in the design
  * notes of the repository):
@@ -596,16 +601,124 @@ static int check_grid(const or_lattice *L, int64_t nx, int64_t ny, int64_t nz)
     return 0;
 }
 
+static int64_t wrap(int64_t v, int64_t n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Walls normal to y                                                          */
+/* ------------------------------------------------------------------------- */
+/* Two plates at y = -1/2 (bottom, side 0) and y = ny - 1/2 (top, side 1), with
+ * temperature th[side] and tangential velocity uw[side] along x; the grid stays
+ * periodic in x and z.  A population that would stream across a plate is
+ * absorbed, its mass credited to the plate and to the (x, z) column of the node
+ * it leaves.  The plate emits the Maxwellian of its own temperature and
+ * velocity: into every pair (direction i entering the domain, node within
+ * |c_iy| layers of the plate) whose streaming source lies behind the plate, it
+ * puts rho_w e_i with e_i = f0_i(1, (uw, 0, 0), th), rho_w taken at the source's
+ * column.  Per column rho_w is fixed by mass balance,
+ *     rho_w * sum_{i entering} min(|c_iy|, ny) e_i = mass absorbed in that column,
+ * so every step conserves mass exactly (diffuse reflection with a discrete,
+ * mass-conserving flux). */
+typedef struct {
+    real th[2], uw[2];
+} or_walls;
+
+static int enters(const or_lattice *L, int side, int i)
+{
+    int cy = L->c[i][1];
+    return side == 0 ? cy > 0 : cy < 0;
+}
+
+/* e_i of one plate and the normalisation sum_{i entering} min(|c_iy|, ny) e_i. */
+static real wall_emission(const or_lattice *L, int N, const or_walls *w, int side, int64_t ny,
+                          real *e)
+{
+    real u[3] = {w->uw[side], 0.0, 0.0};
+    equilibrium(L, N, 1.0, u, w->th[side], e);
+    real z = 0.0;
+    for (int i = 0; i < L->Q; ++i)
+        if (enters(L, side, i)) {
+            int64_t k = L->c[i][1] < 0 ? -L->c[i][1] : L->c[i][1];
+            z += (real)(k < ny ? k : ny) * e[i];
+        }
+    return z;
+}
+
+/* Apply the plates to a state given at the nodes: `src` holds, for every node,
+ * the populations about to stream (AoS); the absorbed mass is summed from the
+ * populations of src that cross a plate, and the emitted values are written
+ * into `dst` (AoS, at the destination nodes).  Column sums run in a fixed order
+ * (y ascending, then i ascending), serially. */
+static int apply_walls(const or_lattice *L, int N, const or_walls *w, int64_t nx, int64_t ny,
+                       int64_t nz, const real *src, real *dst)
+{
+    int Q = L->Q;
+    int64_t ncol = nx * nz;
+    real *rw = (real *)malloc(sizeof(real) * (size_t)(2 * ncol));
+    if (!rw) return -4;
+    real e[2][OR_MAXQ], Z[2];
+    for (int side = 0; side < 2; ++side) Z[side] = wall_emission(L, N, w, side, ny, e[side]);
+    for (int64_t col = 0; col < ncol; ++col) {
+        int64_t x = col % nx, z = col / nx;
+        real m[2] = {0.0, 0.0};
+        for (int64_t y = 0; y < ny; ++y) {
+            const real *fs = &src[((z * ny + y) * nx + x) * Q];
+            for (int i = 0; i < Q; ++i) {
+                int64_t yd = y + L->c[i][1];
+                if (yd < 0) m[0] += fs[i];
+                else if (yd >= ny) m[1] += fs[i];
+            }
+        }
+        rw[col] = m[0] / Z[0];
+        rw[ncol + col] = m[1] / Z[1];
+    }
+    for (int64_t col = 0; col < ncol; ++col) {
+        int64_t x = col % nx, z = col / nx;
+        for (int side = 0; side < 2; ++side)
+            for (int i = 0; i < Q; ++i) {
+                if (!enters(L, side, i)) continue;
+                int64_t k = L->c[i][1] < 0 ? -L->c[i][1] : L->c[i][1];
+                for (int64_t j = 0; j < k && j < ny; ++j) {
+                    int64_t yd = side == 0 ? j : ny - 1 - j;
+                    int64_t xs = wrap(x - L->c[i][0], nx), zs = wrap(z - L->c[i][2], nz);
+                    dst[((z * ny + yd) * nx + x) * Q + i] = rw[side * ncol + zs * nx + xs] * e[side][i];
+                }
+            }
+    }
+    free(rw);
+    return 0;
+}
+
+static int read_walls(const real *walls, or_walls *w)
+{
+    if (!walls) return 0;
+    for (int s = 0; s < 2; ++s) {
+        w->th[s] = walls[s];
+        w->uw[s] = walls[2 + s];
+        if (!(w->th[s] > 0.0)) return -1;
+    }
+    return 1;
+}
+
 /* Fields are SoA: rho[N], u[a*N + cell], theta[N], g[a*N + cell];
  * populations are AoS: f[cell*Q + i]; cell = (z*ny + y)*nx + x. */
+/* walls: NULL (periodic) or {theta_b, theta_t, U_b, U_t}.  With walls, the
+ * populations that would stream in from behind a plate are then replaced by
+ * the plate's emission balancing the initial populations that stream out. */
 int oracle_init(int lattice, int64_t nx, int64_t ny, int64_t nz, int eq_order, int force_order,
-                const real *rho, const real *u, const real *theta, const real *g,
-                real *f, int nthreads)
+                const real *walls, const real *rho, const real *u, const real *theta,
+                const real *g, real *f, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (check_grid(L, nx, ny, nz)) return -1;
     int N = eq_order_of(L, eq_order), nf, ws;
     if (N < 0 || force_terms(force_order, &nf, &ws)) return -2;
+    or_walls w;
+    int has_walls = read_walls(walls, &w);
+    if (has_walls < 0) return -3;
     int64_t ncell = nx * ny * nz;
     int D = L->D, Q = L->Q;
     set_threads(nthreads);
@@ -621,29 +734,66 @@ int oracle_init(int lattice, int64_t nx, int64_t ny, int64_t nz, int eq_order, i
         body_force(L, nf, 0, rho[x], uu, theta[x], gg, sig, F);
         for (int i = 0; i < Q; ++i) f[x * Q + i] = feq[i] - 0.5 * F[i];
     }
+    if (has_walls) return apply_walls(L, N, &w, nx, ny, nz, f, f);
     return 0;
 }
 
-static int64_t wrap(int64_t v, int64_t n)
+/* Steps between plates: collide every node (post-collision values kept at the
+ * node), push what stays inside (periodic in x and z), then let the plates
+ * absorb what crosses them and emit into the slots behind them. */
+static int step_walls(const or_lattice *L, int N, int nf, int ws, const or_walls *w,
+                      int64_t nx, int64_t ny, int64_t nz, real tau_hat, real mu, const real *g,
+                      real *f, real *tmp, int64_t nsteps)
 {
-    v %= n;
-    return v < 0 ? v + n : v;
+    int64_t ncell = nx * ny * nz;
+    int D = L->D, Q = L->Q;
+    real *post = (real *)malloc(sizeof(real) * (size_t)ncell * (size_t)Q);
+    if (!post) return -4;
+    int st = 0;
+    for (int64_t s = 0; s < nsteps && st == 0; ++s) {
+#pragma omp parallel for schedule(static)
+        for (int64_t cell = 0; cell < ncell; ++cell) {
+            real gg[3] = {0, 0, 0};
+            for (int a = 0; a < D; ++a) gg[a] = g[a * ncell + cell];
+            collide_cell(L, N, nf, ws, tau_hat, mu, &f[cell * Q], gg, &post[cell * Q]);
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t cell = 0; cell < ncell; ++cell) {
+            int64_t x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
+            for (int i = 0; i < Q; ++i) {
+                int64_t yd = y + L->c[i][1];
+                if (yd < 0 || yd >= ny) continue;  /* absorbed by a plate */
+                int64_t xd = wrap(x + L->c[i][0], nx);
+                int64_t zd = wrap(z + L->c[i][2], nz);
+                tmp[((zd * ny + yd) * nx + xd) * Q + i] = post[cell * Q + i];
+            }
+        }
+        st = apply_walls(L, N, w, nx, ny, nz, post, tmp);
+        memcpy(f, tmp, (size_t)ncell * (size_t)Q * sizeof(real));
+    }
+    free(post);
+    return st;
 }
 
 /* nsteps collide-then-push steps; f holds the result, tmp is scratch. */
 /* mu = 0: constant tau_hat; mu > 0: per-cell tau^ = mu/(rho theta) + 1/2. */
 int oracle_step(int lattice, int64_t nx, int64_t ny, int64_t nz, real tau_hat, real mu,
-                int eq_order, int force_order, const real *g, real *f, real *tmp,
-                int64_t nsteps, int nthreads)
+                int eq_order, int force_order, const real *walls, const real *g, real *f,
+                real *tmp, int64_t nsteps, int nthreads)
 {
     const or_lattice *L = get_lattice(lattice);
     if (check_grid(L, nx, ny, nz)) return -1;
     int N = eq_order_of(L, eq_order), nf, ws;
     if (N < 0 || force_terms(force_order, &nf, &ws)) return -2;
     if (!(mu >= 0.0) || (mu == 0.0 && !(tau_hat > 0.5))) return -3;
+    or_walls w;
+    int has_walls = read_walls(walls, &w);
+    if (has_walls < 0) return -3;
     int64_t ncell = nx * ny * nz;
     int D = L->D, Q = L->Q;
     set_threads(nthreads);
+    if (has_walls) return step_walls(L, N, nf, ws, &w, nx, ny, nz, tau_hat, mu, g, f, tmp,
+                                     nsteps);
     real *src = f, *dst = tmp;
     for (int64_t s = 0; s < nsteps; ++s) {
 #pragma omp parallel for schedule(static)
