@@ -84,6 +84,7 @@ typedef enum { LBM_G_UNIFORM = 0, LBM_G_AXIS_PROFILE = 1, LBM_G_FIELD = 2 } lbm_
 
 /* lbm_params.flags */
 #define LBM_FLAG_FORCE_FIELD 1u /* reserve workspace for an LBM_G_FIELD force */
+#define LBM_FLAG_WALLS 2u       /* reserve workspace for plates (lbm_set_walls) */
 
 typedef struct {
     uint32_t struct_size; /* = sizeof(lbm_params); ABI versioning */
@@ -197,6 +198,25 @@ LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
  * Takes effect at the next step; batches and graphs that hold the handle must
  * be rebuilt (they refuse to run stale).  LBM_EINVAL if mu < 0 or not finite. */
 LBM_API lbm_status lbm_set_viscosity(lbm_sim *s, double mu);
+
+/* Plates normal to y, for the channel flow of Sec. 3 (the paper does not
+ * publish its wall condition; this one is the library's own).  enable != 0
+ * puts plates at y = -1/2 and y = ny - 1/2 (x and z stay periodic) with
+ * temperatures theta_b, theta_t (> 0) and tangential velocities u_b, u_t along
+ * x.  Diffuse reflection with exact mass conservation: every population that
+ * would stream into a plate is absorbed, its mass credited to the (x, z)
+ * column of the node it leaves; the plate emits f0_i(1, (u_w, 0, 0), theta_w)
+ * times a per-column density into every slot whose streaming source lies
+ * behind it, the density fixed so that each column re-emits exactly what it
+ * absorbed.  Needs LBM_FLAG_WALLS at creation and step count 0; the state is
+ * rebuilt from the moments the handle reports (f~ = f0 - F/2 at every node,
+ * then the populations that would come from behind a plate replaced by its
+ * emission balancing the initial outgoing populations).  enable = 0 removes
+ * the plates.  Handles with plates cannot join a batch (LBM_EUNSUPPORTED from
+ * lbm_batch_set).  LBM_EINVAL on bad values, a missing flag or a stepped
+ * handle. */
+LBM_API lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double theta_t,
+                                 double u_b, double u_t);
 
 /* ---- batching: several simulations per launch, and captured step loops ---- */
 

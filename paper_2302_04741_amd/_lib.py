@@ -24,13 +24,15 @@ LATTICES = {"D2Q37": 0, "D3Q39": 1}
 STORAGES = {"f64": 0, "f32": 1, "f16dev": 2}
 FORCE_KINDS = {"uniform": 0, "axis": 1, "field": 2}
 FLAG_FORCE_FIELD = 1
+FLAG_WALLS = 2
 
 #: the C-ABI entry points, in the order include/lbm.h declares them
 API_SYMBOLS = (
     "lbm_workspace_bytes", "lbm_create", "lbm_set_force", "lbm_step", "lbm_moments",
     "lbm_destroy", "lbm_last_error", "lbm_totals", "lbm_heat_flux", "lbm_population_bytes",
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
-    "lbm_set_stream", "lbm_set_block", "lbm_set_viscosity", "lbm_batch_workspace_bytes",
+    "lbm_set_stream", "lbm_set_block", "lbm_set_viscosity", "lbm_set_walls",
+    "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_set", "lbm_batch_step", "lbm_batch_set_launch",
     "lbm_batch_destroy",
     "lbm_graph_create", "lbm_graph_launch", "lbm_graph_destroy", "lbm_lattice_table",
@@ -112,6 +114,9 @@ def load() -> ctypes.CDLL:
     L.lbm_set_block.restype = _i32
     L.lbm_set_viscosity.argtypes = [_vp, ctypes.c_double]
     L.lbm_set_viscosity.restype = _i32
+    _d = ctypes.c_double
+    L.lbm_set_walls.argtypes = [_vp, _i32, _d, _d, _d, _d]
+    L.lbm_set_walls.restype = _i32
     L.lbm_batch_workspace_bytes.argtypes = [_i32]
     L.lbm_batch_workspace_bytes.restype = _sz
     L.lbm_batch_create.argtypes = [_i32, _vp, _sz, _vp, ctypes.POINTER(_vp)]
@@ -145,7 +150,8 @@ def check(status: int) -> int:
 
 
 def make_params(lattice: str, dims, tau_hat: float, storage: str = "f64", eq_order: int = 0,
-                force_order: int = 4, force_field: bool = False, rho0: float = 1.0) -> lbm_params:
+                force_order: int = 4, force_field: bool = False, rho0: float = 1.0,
+                walls: bool = False) -> lbm_params:
     nx, ny, nz = (tuple(int(d) for d in dims) + (1, 1))[:3]
     p = lbm_params()
     p.struct_size = ctypes.sizeof(lbm_params)
@@ -153,7 +159,7 @@ def make_params(lattice: str, dims, tau_hat: float, storage: str = "f64", eq_ord
     p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
     p.eq_order = int(eq_order)
     p.force_order = int(force_order)
-    p.flags = FLAG_FORCE_FIELD if force_field else 0
+    p.flags = (FLAG_FORCE_FIELD if force_field else 0) | (FLAG_WALLS if walls else 0)
     p.nx, p.ny, p.nz = nx, ny, nz
     p.tau_hat = float(tau_hat)
     p.rho0 = float(rho0)

@@ -35,7 +35,10 @@ struct lbm_sim {
     double *totals_dev;
     int64_t step;
     int block;
-    int64_t gen;  // bumped when launch arguments change (force, block, stream)
+    int64_t gen;  // bumped when launch arguments change (force, block, stream, plates)
+    WallDesc wd;  // plates (off unless lbm_set_walls)
+    double *wall_rw;
+    double *wall_e;
 };
 
 namespace {
@@ -74,8 +77,8 @@ size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : (storage == 
 size_t arith_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t pop, gtab, partials, totals;
-    size_t off_pop1, off_gtab, off_part, off_tot, total;
+    size_t pop, gtab, partials, totals, walls;
+    size_t off_pop1, off_gtab, off_part, off_tot, off_walls, total;
 };
 
 int64_t row_pitch(int64_t nx) { return (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
@@ -101,7 +104,13 @@ Layout layout_of(const lbm_params *p)
     L.off_gtab = 2 * L.pop;
     L.off_part = L.off_gtab + L.gtab;
     L.off_tot = L.off_part + L.partials;
-    L.total = L.off_tot + L.totals;
+    // plates: wall densities [2][nx*nz], emission tables [2][Q + 1]
+    L.walls = (p->flags & LBM_FLAG_WALLS)
+                  ? align_up(2 * size_t(p->nx) * size_t(p->nz) * sizeof(double)) +
+                        align_up(2 * size_t(Q + 1) * sizeof(double))
+                  : 0;
+    L.off_walls = L.off_tot + L.totals;
+    L.total = L.off_walls + L.walls;
     return L;
 }
 
@@ -135,13 +144,39 @@ lbm_status check_params(const lbm_params *p)
                     p->eq_order, lattice_maxeq(p->lattice));
     if (p->force_order < LBM_FORCE_N0 || p->force_order > LBM_FORCE_N2)
         return fail(LBM_EINVAL, "unknown force_order %d", p->force_order);
-    if (p->flags & ~LBM_FLAG_FORCE_FIELD) return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(LBM_FLAG_FORCE_FIELD | LBM_FLAG_WALLS))
+        return fail(LBM_EINVAL, "unknown flags 0x%x", p->flags);
     if (!std::isfinite(p->rho0) || !(p->rho0 >= 0))
         return fail(LBM_EINVAL, "rho0 must be finite and >= 0 (got %g)", p->rho0);
     return LBM_OK;
 }
 
-LaunchCfg cfg(const lbm_sim *s) { return LaunchCfg{s->block, s->stream}; }
+LaunchCfg cfg(const lbm_sim *s) { return LaunchCfg{s->block, s->stream, s->wd}; }
+
+// With plates, the wall densities of the current state come first.
+hipError_t wall_densities(const lbm_sim *s)
+{
+    if (!s->wd.on) return hipSuccess;
+    return launch_wall_mass(s->p.lattice, s->p.storage, s->pop[s->cur], s->gd, s->co, cfg(s));
+}
+
+// One time step: K1 over every row, then, with plates, the rows next to them
+// again with the plates' emission (their densities taken from the same state).
+hipError_t launch_one_step(const lbm_sim *s, int cur)
+{
+    const void *A = s->pop[cur];
+    void *B = s->pop[cur ^ 1];
+    hipError_t e;
+    if (s->wd.on) {
+        e = launch_wall_mass(s->p.lattice, s->p.storage, A, s->gd, s->co, cfg(s));
+        if (e != hipSuccess) return e;
+    }
+    e = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B, s->gd, s->fd,
+                    s->co, cfg(s));
+    if (e != hipSuccess || !s->wd.on) return e;
+    return launch_wall_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B, s->gd,
+                            s->fd, s->co, cfg(s));
+}
 
 }  // namespace
 
@@ -191,6 +226,14 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->fd.tab = s->gtab;
     s->partials = reinterpret_cast<double *>(s->ws + L.off_part);
     s->totals_dev = reinterpret_cast<double *>(s->ws + L.off_tot);
+    s->wd = WallDesc{0, 0, nullptr, nullptr};
+    s->wall_rw = nullptr;
+    s->wall_e = nullptr;
+    if (p->flags & LBM_FLAG_WALLS) {
+        s->wall_rw = reinterpret_cast<double *>(s->ws + L.off_walls);
+        s->wall_e = reinterpret_cast<double *>(
+            s->ws + L.off_walls + align_up(2 * size_t(p->nx) * size_t(p->nz) * sizeof(double)));
+    }
     s->step = 0;
     s->block = 0;
     hipError_t e = launch_init(p->lattice, p->storage, s->eq, p->force_order, rho, u, theta,
@@ -250,6 +293,8 @@ lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis
         // which were produced with the old one.  The idle population buffer
         // holds the FP64 moments in between ((2 + D) doubles per cell fit in
         // Q stored values for every storage type).
+        e = wall_densities(s);
+        if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
         e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], mrho, mu, mth, s->gd, s->fd,
                            s->co, cfg(s));
         if (e != hipSuccess) return dev_fail(e, "moments kernel launch");
@@ -273,8 +318,7 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps)
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
-                                   s->pop[s->cur], s->pop[s->cur ^ 1], s->gd, s->fd, s->co, cfg(s));
+        hipError_t e = launch_one_step(s, s->cur);
         if (e != hipSuccess) return dev_fail(e, "step kernel launch");
         s->cur ^= 1;
         s->step++;
@@ -286,8 +330,10 @@ lbm_status lbm_moments(lbm_sim *s, double *rho, double *u, double *theta)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (!rho && !u && !theta) return ok();
-    hipError_t e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], rho, u, theta,
-                                  s->gd, s->fd, s->co, cfg(s));
+    hipError_t e = wall_densities(s);
+    if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
+    e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], rho, u, theta, s->gd, s->fd,
+                       s->co, cfg(s));
     if (e != hipSuccess) return dev_fail(e, "moments kernel launch");
     return ok();
 }
@@ -317,8 +363,10 @@ lbm_status lbm_heat_flux(lbm_sim *s, double *q)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (!q) return fail(LBM_EINVAL, "q is NULL");
-    hipError_t e = launch_heat_flux(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
-                                    s->pop[s->cur], q, s->gd, s->fd, s->co, cfg(s));
+    hipError_t e = wall_densities(s);
+    if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
+    e = launch_heat_flux(s->p.lattice, s->p.storage, s->eq, s->p.force_order, s->pop[s->cur], q,
+                         s->gd, s->fd, s->co, cfg(s));
     if (e != hipSuccess) return dev_fail(e, "heat-flux kernel launch");
     return ok();
 }
@@ -395,6 +443,42 @@ lbm_status lbm_set_viscosity(lbm_sim *s, double mu)
     return ok();
 }
 
+lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double theta_t, double u_b,
+                         double u_t)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!(s->p.flags & LBM_FLAG_WALLS))
+        return fail(LBM_EINVAL, "plates need LBM_FLAG_WALLS at creation");
+    if (s->step != 0) return fail(LBM_EINVAL, "plates must be set before the first step");
+    if (enable && (!std::isfinite(theta_b) || !std::isfinite(theta_t) || !(theta_b > 0) ||
+                   !(theta_t > 0) || !std::isfinite(u_b) || !std::isfinite(u_t)))
+        return fail(LBM_EINVAL, "plate temperatures must be finite and > 0, velocities finite");
+    // Rebuild the state for the new boundary from the moments it reports now.
+    hipError_t e;
+    void *scratch = s->pop[s->cur ^ 1];
+    double *mrho = static_cast<double *>(scratch);
+    double *mu = mrho + s->N;
+    double *mth = mu + int64_t(s->D) * s->N;
+    e = wall_densities(s);
+    if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
+    e = launch_moments(s->p.lattice, s->p.storage, s->pop[s->cur], mrho, mu, mth, s->gd, s->fd,
+                       s->co, cfg(s));
+    if (e != hipSuccess) return dev_fail(e, "moments kernel launch");
+    if (enable) {
+        const double th[2] = {theta_b, theta_t}, uw[2] = {u_b, u_t};
+        e = launch_wall_setup(s->p.lattice, s->eq, th, uw, s->p.ny, s->wall_e, s->stream);
+        if (e != hipSuccess) return dev_fail(e, "plate setup kernel launch");
+        s->wd = WallDesc{1, 0, s->wall_rw, s->wall_e};
+    } else {
+        s->wd = WallDesc{0, 0, nullptr, nullptr};
+    }
+    s->gen++;
+    e = launch_init(s->p.lattice, s->p.storage, s->eq, s->p.force_order, mrho, mu, mth,
+                    s->pop[s->cur], s->gd, s->fd, s->co, cfg(s));
+    if (e != hipSuccess) return dev_fail(e, "init kernel launch");
+    return ok();
+}
+
 int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
 {
     if (lattice != LBM_D2Q37 && lattice != LBM_D3Q39)
@@ -410,7 +494,7 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.3.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.4.0"; }
 
 // ---------------------------------------------------------------------------
 // batches
@@ -498,6 +582,7 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
             s->p.force_order != s0->p.force_order)
             return fail(LBM_EINVAL,
                         "batch members must share lattice, storage, eq_order and force_order");
+        if (s->wd.on) return fail(LBM_EUNSUPPORTED, "sims[%d] has plates; batches are periodic", k);
         TileSim &t = tab[k];
         t.pop[0] = s->pop[0];
         t.pop[1] = s->pop[1];
@@ -668,9 +753,7 @@ lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph 
     if (s) {
         const int cur0 = s->cur;
         for (int64_t k = 0; k < nsteps && st == LBM_OK; ++k) {
-            hipError_t el = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
-                                        s->pop[s->cur], s->pop[s->cur ^ 1], s->gd, s->fd, s->co,
-                                        cfg(s));
+            hipError_t el = launch_one_step(s, s->cur);
             if (el != hipSuccess) st = dev_fail(el, "step launch during capture");
             s->cur ^= 1;
         }

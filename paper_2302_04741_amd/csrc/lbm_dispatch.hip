@@ -26,6 +26,37 @@ hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_wall_setup(int lat, int eq, const double *theta, const double *uw, int64_t ny,
+                             double *e, hipStream_t stream)
+{
+    if (lat == 0) return launch_wall_setup_l<0>(eq, theta, uw, ny, e, stream);
+    if (lat == 1) return launch_wall_setup_l<1>(eq, theta, uw, ny, e, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wall_mass(int lat, int storage, const void *A, const GridDims &gd,
+                            const StepCoef &co, const LaunchCfg &lc)
+{
+    if (lat == 0) return launch_wall_mass_l<0>(storage, A, gd, co, lc);
+    if (lat == 1) return launch_wall_mass_l<1>(storage, A, gd, co, lc);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wall_step(int lat, int storage, int eq, int fo, const void *A, void *B,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc)
+{
+#define LBM_WS(L, S) return launch_wall_step_ls<L, S>(eq, fo, A, B, gd, fd, co, lc)
+    if (lat == 0 && storage == 0) LBM_WS(0, double);
+    if (lat == 0 && storage == 1) LBM_WS(0, float);
+    if (lat == 0 && storage == 2) LBM_WS(0, __half);
+    if (lat == 1 && storage == 0) LBM_WS(1, double);
+    if (lat == 1 && storage == 1) LBM_WS(1, float);
+    if (lat == 1 && storage == 2) LBM_WS(1, __half);
+#undef LBM_WS
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl)
 {
 #define LBM_MS(L, S) return launch_multi_step_ls<L, S>(eq, fo, bl)

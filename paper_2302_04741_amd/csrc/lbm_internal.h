@@ -506,9 +506,22 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Plates normal to y at y = -1/2 and y = ny - 1/2 (lbm_set_walls): a population
+// whose streaming source lies behind a plate is the plate's emission
+// rw[side][column of the source] * e[side][i]; populations streaming into a
+// plate stay in their slots at the node they leave (the "crossing" slots),
+// from which rw is computed before every use (wall_mass_kernel).
+struct WallDesc {
+    int32_t on;
+    int32_t pad;
+    double *rw;       // [2][nx*nz] wall densities of the current state (bottom, top)
+    const double *e;  // [2][Q + 1]: e_i = f0_i(1, (U_w, 0, 0), theta_w), then the normalisation
+};
+
 struct LaunchCfg {
     int block;  // threads along x per block
     hipStream_t stream;
+    WallDesc walls;  // off unless the handle has plates
 };
 
 // Generic entry points (lbm_dispatch.hip), switching on lattice and storage.
@@ -540,6 +553,14 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl);
+// plates: emission tables, wall densities, and the step of the rows next to them
+hipError_t launch_wall_setup(int lat, int eq, const double *theta, const double *uw, int64_t ny,
+                             double *e, hipStream_t stream);
+hipError_t launch_wall_mass(int lat, int storage, const void *A, const GridDims &gd,
+                            const StepCoef &co, const LaunchCfg &lc);
+hipError_t launch_wall_step(int lat, int storage, int eq, int fo, const void *A, void *B,
+                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                            const LaunchCfg &lc);
 
 // Per-lattice / per-storage pieces, each explicitly instantiated in its own
 // translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
@@ -548,6 +569,15 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
                           const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
 template <int LAT, class S>
 hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl);
+template <int LAT, class S>
+hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
+                               const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
+template <int LAT>
+hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, int64_t ny,
+                               double *e, hipStream_t stream);
+template <int LAT>
+hipError_t launch_wall_mass_l(int storage, const void *A, const GridDims &gd, const StepCoef &co,
+                              const LaunchCfg &lc);
 template <int LAT>
 hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
                          const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,

@@ -57,9 +57,23 @@ template <class L> struct Codec<L, __half> {
 // ---------------------------------------------------------------------------
 // pull gather: h_i = A[i][x - c_i (periodic)]
 // ---------------------------------------------------------------------------
-template <class L, class S, class T>
+// Deviation h_i = f_i - w_i rho0 that the plate emits into (x, y, z) along c_i
+// (the source (x, y, z) - c_i lies behind the plate: side 0 below, 1 above).
+template <class L>
+__device__ __forceinline__ double wall_emitted(const WallDesc &wd, const GridDims &gd, int i,
+                                               double w, double rho0, int x, int y, int z)
+{
+    const int side = y - L::c(i, 1) < 0 ? 0 : 1;
+    const int xv = wrap3(x - L::c(i, 0), gd.nx);
+    const int zv = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
+    const int64_t ncol = int64_t(gd.nx) * gd.nz;
+    return wd.rw[side * ncol + int64_t(zv) * gd.nx + xv] * wd.e[side * (L::Q + 1) + i] - w * rho0;
+}
+
+template <class L, class S, class T, bool WALLS = false>
 __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &gd, int x, int y,
-                                       int z, T (&h)[L::Q])
+                                       int z, T (&h)[L::Q], const WallDesc *wd = nullptr,
+                                       double rho0 = 0.0)
 {
     // x offsets are per lane (7 distinct byte offsets); y and z are uniform over
     // the block, so each row offset and each plane resource is a scalar.
@@ -76,6 +90,13 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+        if constexpr (WALLS) {
+            const int ysrc = y - cy;  // uniform over the block
+            if (ysrc < 0 || ysrc >= gd.ny) {
+                h[i] = T(wall_emitted<L>(*wd, gd, i, L::wshell(L::shell(i)), rho0, x, y, z));
+                return;
+            }
+        }
         const uint32_t row =
             uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px) * uint32_t(sizeof(S));
         const auto r = plane_rsrc(A + int64_t(i) * P, plane_bytes);
@@ -95,10 +116,11 @@ template <class S> constexpr int step_max_threads()
 
 // The fused update of one cell (x, y, z): gather, moments, equilibrium, stress,
 // force, relaxation, store.  y and z must be uniform over the wavefront.
-template <int LAT, class S, int EQ, int FO>
+template <int LAT, class S, int EQ, int FO, bool WALLS = false>
 __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict__ B,
                                           const GridDims &gd, const ForceDesc &fd,
-                                          const StepCoef &co, int x, int y, int z)
+                                          const StepCoef &co, int x, int y, int z,
+                                          const WallDesc *wd = nullptr)
 {
     using L = Lattice<LAT>;
     using T = typename ArithOf<S>::type;
@@ -110,7 +132,7 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // offsets address it
 
     T h[L::Q];
-    gather<L, S, T>(A, gd, x, y, z, h);
+    gather<L, S, T, WALLS>(A, gd, x, y, z, h, wd, co.rho0);
     T g[3];
     load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
 
@@ -152,6 +174,21 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= gd.nx) return;
     step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
+}
+
+// K1c: the rows next to the plates (y < 3 and y >= ny - 3; every row when
+// ny <= 6), run after K1 has updated every row as if periodic: the same cell
+// update with the plates' emission in place of the sources behind them.
+template <int LAT, class S, int EQ, int FO>
+__global__ void __launch_bounds__(step_max_threads<S>())
+    wall_step_kernel(const S *__restrict__ A, S *__restrict__ B, GridDims gd, ForceDesc fd,
+                     StepCoef co, WallDesc wd)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y, z = blockIdx.z;
+    const int y = (gd.ny <= 6 || k < 3) ? k : gd.ny - 6 + k;
+    if (x >= gd.nx) return;
+    step_cell<LAT, S, EQ, FO, true>(A, B, gd, fd, co, x, y, z, &wd);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,8 +252,10 @@ __device__ __forceinline__ void store_any(void *A, int storage, int64_t idx, dou
 
 template <class L>
 __device__ __forceinline__ void gather_any(const void *A, int storage, const GridDims &gd, int x,
-                                           int y, int z, double (&h)[L::Q])
+                                           int y, int z, double (&h)[L::Q],
+                                           const WallDesc &wd, double rho0)
 {
+    const bool near = wd.on && (y < 3 || y >= gd.ny - 3);
     int xs[7], ys[7], zs[7];
 #pragma unroll
     for (int d = 0; d < 7; ++d) {
@@ -227,6 +266,10 @@ __device__ __forceinline__ void gather_any(const void *A, int storage, const Gri
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+        if (near && (y - cy < 0 || y - cy >= gd.ny)) {
+            h[i] = wall_emitted<L>(wd, gd, i, L::wshell(L::shell(i)), rho0, x, y, z);
+            return;
+        }
         const int64_t idx =
             int64_t(i) * gd.P + (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px + xs[cx + 3];
         h[i] = load_any<L, i>(A, storage, idx);
@@ -254,7 +297,7 @@ template <int LAT, int EQ, int FO>
 __global__ void __launch_bounds__(256)
     init_kernel(const double *__restrict__ rho, const double *__restrict__ u,
                 const double *__restrict__ theta, void *__restrict__ A, int storage, GridDims gd,
-                ForceDesc fd, StepCoef co)
+                ForceDesc fd, StepCoef co, WallDesc wd)
 {
     using L = Lattice<LAT>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,6 +326,16 @@ __global__ void __launch_bounds__(256)
         constexpr double w = L::wshell(L::shell(ip));
         auto put = [&](auto II, double v) {
             constexpr int i = decltype(II)::value;
+            if (wd.on) {
+                // with plates: a population arriving from behind a plate has no
+                // slot (the plate emits it); one about to stream into a plate
+                // stays in its own node's slot
+                if (y + L::c(i, 1) < 0 || y + L::c(i, 1) >= gd.ny) {
+                    const int64_t own = (int64_t(z) * gd.ny + y) * gd.px + x;
+                    store_any<L, i>(A, storage, int64_t(i) * gd.P + own, v);
+                }
+                if (y - L::c(i, 1) < 0 || y - L::c(i, 1) >= gd.ny) return;
+            }
             const int xd = wrap3(x - L::c(i, 0), gd.nx);
             const int yd = wrap3(y - L::c(i, 1), gd.ny);
             const int zd = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
@@ -302,7 +355,7 @@ template <int LAT>
 __global__ void __launch_bounds__(256)
     moments_kernel(const void *__restrict__ A, int storage, double *__restrict__ rho,
                    double *__restrict__ u, double *__restrict__ theta, GridDims gd, ForceDesc fd,
-                   StepCoef co)
+                   StepCoef co, WallDesc wd)
 {
     using L = Lattice<LAT>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,7 +364,7 @@ __global__ void __launch_bounds__(256)
     const int64_t N = gd.N;
     const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
     double h[L::Q];
-    gather_any<L>(A, storage, gd, x, y, z, h);
+    gather_any<L>(A, storage, gd, x, y, z, h, wd, co.rho0);
     double g[3];
     force_any(fd, storage, gd, L::D, x, y, z, cell, g);
     const RawSums<double> rs = raw_sums<L, double>(h);
@@ -331,7 +384,7 @@ __global__ void __launch_bounds__(256)
 template <int LAT, int EQ, int FO>
 __global__ void __launch_bounds__(256)
     heatflux_kernel(const void *__restrict__ A, int storage, double *__restrict__ q, GridDims gd,
-                    ForceDesc fd, StepCoef co)
+                    ForceDesc fd, StepCoef co, WallDesc wd)
 {
     using L = Lattice<LAT>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,7 +393,7 @@ __global__ void __launch_bounds__(256)
     const int64_t N = gd.N;
     const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
     double h[L::Q];
-    gather_any<L>(A, storage, gd, x, y, z, h);
+    gather_any<L>(A, storage, gd, x, y, z, h, wd, co.rho0);
     double g[3];
     force_any(fd, storage, gd, L::D, x, y, z, cell, g);
     const RawSums<double> rs = raw_sums<L, double>(h);
@@ -367,6 +420,84 @@ __global__ void __launch_bounds__(256)
             if constexpr (im >= 0) acc(IM, base + cf * h[im] + (ev - od));
         });
     for (int a = 0; a < L::D; ++a) q[int64_t(a) * N + cell] = 0.5 * qa[a];
+}
+
+// ---------------------------------------------------------------------------
+// K6: plates.  wall_setup_kernel: e_i = f0_i(1, (U_w, 0, 0), theta_w) of both
+// plates in FP64 and the normalisation sum_{i entering} min(|c_iy|, ny) e_i.
+// wall_mass_kernel: per (x, z) column and plate, the mass of the crossing
+// slots (populations about to stream into the plate, rows y < 3 or
+// y >= ny - 3, summed y ascending then i ascending) over that normalisation:
+// the density rw at which the plate re-emits exactly what it absorbs.
+// ---------------------------------------------------------------------------
+template <int LAT, int EQ>
+__global__ void __launch_bounds__(64)
+    wall_setup_kernel(double th_b, double th_t, double u_b, double u_t, int64_t ny,
+                      double *__restrict__ e)
+{
+    using L = Lattice<LAT>;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int side = 0; side < 2; ++side) {
+        CellState<double> cs;
+        cs.rho = 1.0;
+        cs.drho = 0.0;
+        cs.th = side == 0 ? th_b : th_t;
+        for (int a = 0; a < 3; ++a) {
+            cs.ub[a] = 0.0;
+            cs.g[a] = 0.0;
+            for (int b = 0; b < 3; ++b) cs.sig[a][b] = 0.0;
+        }
+        cs.ub[0] = side == 0 ? u_b : u_t;
+        cs.om = 0.0;
+        cs.cf = 0.0;
+        double *es = e + side * (L::Q + 1);
+        // f0 = w rho + (f0 - w rho); the bracket is combo_pairs' NO_BASE part
+        combo_pairs<L, double, EQ, 1, true>(cs, 1.0, 0.0, [&](auto IP, auto IM, double ev,
+                                                            double od) {
+            constexpr int ip = decltype(IP)::value;
+            constexpr int im = decltype(IM)::value;
+            constexpr double w = L::wshell(L::shell(ip));
+            es[ip] = w + (ev + od);
+            if constexpr (im >= 0) es[im] = w + (ev - od);
+        });
+        double z = 0.0;
+        for (int i = 0; i < L::Q; ++i) {
+            const int cy = L::c(i, 1);
+            if (side == 0 ? cy > 0 : cy < 0) {
+                const int64_t k = cy < 0 ? -cy : cy;
+                z += double(k < ny ? k : ny) * es[i];
+            }
+        }
+        es[L::Q] = z;
+    }
+}
+
+template <int LAT>
+__global__ void __launch_bounds__(256)
+    wall_mass_kernel(const void *__restrict__ A, int storage, GridDims gd, StepCoef co,
+                     WallDesc wd)
+{
+    using L = Lattice<LAT>;
+    const int64_t ncol = int64_t(gd.nx) * gd.nz;
+    const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (col >= ncol) return;
+    const int x = int(col % gd.nx), z = int(col / gd.nx);
+    for (int side = 0; side < 2; ++side) {
+        const int y0 = side == 0 ? 0 : (gd.ny > 3 ? gd.ny - 3 : 0);
+        const int y1 = side == 0 ? (gd.ny < 3 ? gd.ny : 3) : gd.ny;
+        double m = 0.0;
+        for (int y = y0; y < y1; ++y) {
+            const int64_t own = (int64_t(z) * gd.ny + y) * gd.px + x;
+            static_for<0, L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const int yd = y + L::c(i, 1);
+                if (side == 0 ? yd < 0 : yd >= gd.ny)
+                    m += load_any<L, i>(A, storage, int64_t(i) * gd.P + own) +
+                         L::wshell(L::shell(i)) * co.rho0;
+            });
+        }
+        wd.rw[side * ncol + col] = m / wd.e[side * (L::Q + 1) + L::Q];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -72,7 +72,7 @@ hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const d
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((init_kernel<LAT, decltype(E)::value, decltype(O)::value>),
                            cell_grid(gd, bx), dim3(bx), 0, lc.stream, rho, u, theta, A, storage,
-                           gd, fd, co);
+                           gd, fd, co, lc.walls);
         return hipGetLastError();
     });
 }
@@ -84,7 +84,7 @@ hipError_t launch_moments_l(int storage, const void *A, double *rho, double *u, 
 {
     const int bx = block_for(gd, 256);
     hipLaunchKernelGGL((moments_kernel<LAT>), cell_grid(gd, bx), dim3(bx), 0, lc.stream, A,
-                       storage, rho, u, theta, gd, fd, co);
+                       storage, rho, u, theta, gd, fd, co, lc.walls);
     return hipGetLastError();
 }
 
@@ -96,9 +96,50 @@ hipError_t launch_heat_flux_l(int storage, int eq, int fo, const void *A, double
     const int bx = block_for(gd, 256);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((heatflux_kernel<LAT, decltype(E)::value, decltype(O)::value>),
-                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, A, storage, q, gd, fd, co);
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, A, storage, q, gd, fd, co,
+                           lc.walls);
         return hipGetLastError();
     });
+}
+
+template <int LAT, class S>
+hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
+                               const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
+{
+    const int bx = block_for(gd, lc.block > 0 ? std::min(lc.block, step_max_threads<S>()) : 256);
+    const dim3 grid(unsigned((gd.nx + bx - 1) / bx), unsigned(gd.ny < 6 ? gd.ny : 6),
+                    unsigned(gd.nz));
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        hipLaunchKernelGGL((wall_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
+                           grid, dim3(bx), 0, lc.stream, static_cast<const S *>(A),
+                           static_cast<S *>(B), gd, fd, co, lc.walls);
+        return hipGetLastError();
+    });
+}
+
+template <int LAT>
+hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, int64_t ny,
+                               double *e, hipStream_t stream)
+{
+    hipError_t r = hipErrorInvalidValue;
+    static_for<2, Lattice<LAT>::MAXEQ + 1>([&](auto E) {
+        if (eq == decltype(E)::value) {
+            hipLaunchKernelGGL((wall_setup_kernel<LAT, decltype(E)::value>), dim3(1), dim3(64), 0,
+                               stream, theta[0], theta[1], uw[0], uw[1], ny, e);
+            r = hipGetLastError();
+        }
+    });
+    return r;
+}
+
+template <int LAT>
+hipError_t launch_wall_mass_l(int storage, const void *A, const GridDims &gd, const StepCoef &co,
+                              const LaunchCfg &lc)
+{
+    const int64_t ncol = int64_t(gd.nx) * gd.nz;
+    hipLaunchKernelGGL((wall_mass_kernel<LAT>), dim3(unsigned((ncol + 255) / 256)), dim3(256), 0,
+                       lc.stream, A, storage, gd, co, lc.walls);
+    return hipGetLastError();
 }
 
 template <int LAT>

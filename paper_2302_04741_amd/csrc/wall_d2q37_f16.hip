@@ -1,0 +1,8 @@
+// Step of the rows next to the plates for D2Q37 storage f16 (all equilibrium and force orders).
+#include "lbm_launch.h"
+
+namespace lbm {
+template hipError_t launch_wall_step_ls<0, __half>(int, int, const void *, void *, const GridDims &,
+                                               const ForceDesc &, const StepCoef &,
+                                               const LaunchCfg &);
+}  // namespace lbm

@@ -1,0 +1,8 @@
+// Step of the rows next to the plates for D3Q39 storage f32 (all equilibrium and force orders).
+#include "lbm_launch.h"
+
+namespace lbm {
+template hipError_t launch_wall_step_ls<1, float>(int, int, const void *, void *, const GridDims &,
+                                               const ForceDesc &, const StepCoef &,
+                                               const LaunchCfg &);
+}  // namespace lbm

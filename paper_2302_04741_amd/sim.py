@@ -50,7 +50,7 @@ class Sim:
 
     def __init__(self, lattice: str, dims, tau_hat: float, rho, u, theta, *, storage="f64",
                  eq_order: int = 0, force_order: int = 4, force_field: bool = False,
-                 rho0: float | None = None, device=None, stream=None):
+                 rho0: float | None = None, walls: bool = False, device=None, stream=None):
         torch = _torch()
         L = load()
         self.lattice = lattice
@@ -66,7 +66,7 @@ class Sim:
         self.device = torch.device(device if device is not None else "cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.params = _lib.make_params(lattice, self.dims, tau_hat, storage, eq_order,
-                                       force_order, force_field, rho0)
+                                       force_order, force_field, rho0, walls)
         nbytes = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             # invalid parameters: let lbm_create report why
@@ -228,6 +228,13 @@ class Sim:
         dynamic viscosity held constant); 0: the constant tau_hat again."""
         check(load().lbm_set_viscosity(self.handle, float(mu)))
 
+    def set_walls(self, theta_b: float, theta_t: float, u_b: float = 0.0, u_t: float = 0.0,
+                  enable: bool = True):
+        """Plates at y = -1/2 and y = ny - 1/2 with temperatures and tangential
+        velocities (needs walls=True at creation and step count 0)."""
+        check(load().lbm_set_walls(self.handle, int(bool(enable)), float(theta_b),
+                                   float(theta_t), float(u_b), float(u_t)))
+
     def set_block(self, threads: int):
         check(load().lbm_set_block(self.handle, int(threads)))
 
@@ -240,10 +247,15 @@ def from_workload(wl, storage="f64", **kw) -> Sim:
     """Create a Sim for a workloads.Workload and apply its force."""
     force_field = wl.force[0] == "field"
     s = Sim(wl.lattice, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, storage=storage,
-            eq_order=wl.eq_order, force_order=wl.force_order, force_field=force_field, **kw)
-    s.set_workload_force(wl.force)
+            eq_order=wl.eq_order, force_order=wl.force_order, force_field=force_field,
+            walls=wl.walls is not None, **kw)
     if wl.mu > 0:
         s.set_viscosity(wl.mu)
+    s.set_workload_force(wl.force)
+    if wl.walls is not None:
+        # last: the state is rebuilt from the moments, which equal the inputs
+        # only while the grid is periodic
+        s.set_walls(*wl.walls)
     return s
 
 

@@ -51,6 +51,7 @@ class Workload:
     eq_order: int = 0
     force_order: int = 4
     mu: float = 0.0  # > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2
+    walls: tuple | None = None  # (theta_b, theta_t, U_b, U_t): plates normal to y
 
     @property
     def D(self) -> int:

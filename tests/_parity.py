@@ -30,7 +30,7 @@ def oracle_run(oracle_mod, wl, steps, nthreads=0, prec="f64"):
     sim = oracle_mod.OracleSim(LAT_ID[wl.lattice], wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta,
                                wl.force_field(), eq_order=wl.eq_order,
                                force_order=wl.force_order, nthreads=nthreads, prec=prec,
-                               mu=wl.mu)
+                               mu=wl.mu, walls=wl.walls)
     sim.step(steps)
     return sim
 
