@@ -296,6 +296,8 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=256, help="grid side (default 256)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed regions of --steps steps reported as a spread")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="oracle steps of the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -365,6 +367,16 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_events = ev0.elapsed_time(ev1)
+    # further timed regions of the same length, for the spread (median of 5)
+    rep_ms = []
+    for _ in range(args.repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rep_ms.append(e0.elapsed_time(e1) / args.steps)
     rho, u, th = s.moments()
     finite = bool(torch.isfinite(u).all().item() and torch.isfinite(th).all().item())
     if not finite:
@@ -420,6 +432,12 @@ def main(argv=None) -> int:
         },
         "wall_s_timed_region": round(wall, 4),
     }
+    if rep_ms:
+        med = sorted(rep_ms)[len(rep_ms) // 2]
+        out["repeats"] = {"count": len(rep_ms), "steps_each": args.steps,
+                          "median_mlups": round(N / (med * 1e-3) / 1e6, 1),
+                          "min_mlups": round(N / (max(rep_ms) * 1e-3) / 1e6, 1),
+                          "max_mlups": round(N / (min(rep_ms) * 1e-3) / 1e6, 1)}
     if args.cpu_steps > 0:
         del s, rho, u, th
         torch.cuda.empty_cache()

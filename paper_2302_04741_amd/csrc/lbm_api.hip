@@ -516,6 +516,7 @@ struct lbm_batch {
     int64_t ntiles;
     int threads;     // tile width and block size
     int64_t blocks;  // 0: one block per tile
+    bool upload_pending;  // an asynchronous upload may still read `host`
 };
 
 struct lbm_graph {
@@ -596,15 +597,17 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
         tiles += int64_t(t.chunks_x) * s->p.ny * s->p.nz;
     }
     begin[count] = tiles;
-    // wait for the previous table's readers before overwriting the staging copy
-    if (!b->host.empty()) {
+    // wait for the previous upload before replacing its staging copy
+    if (b->upload_pending) {
         hipError_t e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return dev_fail(e, "stream synchronize");
+        b->upload_pending = false;
     }
     b->host.swap(host);
     hipError_t e = hipMemcpyAsync(b->ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
                                   b->stream);
     if (e != hipSuccess) return dev_fail(e, "tile table upload");
+    b->upload_pending = true;
     b->sims.assign(sims, sims + count);
     b->step_at_set.clear();
     b->gen_at_set.clear();
@@ -661,6 +664,7 @@ lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_
     b->generation = 0;
     b->threads = BATCH_DEFAULT_THREADS;
     b->blocks = 0;
+    b->upload_pending = false;
     *out = b;
     return ok();
 }
@@ -715,7 +719,13 @@ lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks)
     return ok();
 }
 
-void lbm_batch_destroy(lbm_batch *b) { delete b; }
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    // the last tile-table upload reads the host staging copy owned here
+    if (b->upload_pending) (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
 
 // ---------------------------------------------------------------------------
 // captured step loops

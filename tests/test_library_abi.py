@@ -145,6 +145,10 @@ def test_workspace_size(lattice, dims, storage, sbytes, Q, D):
     pf = _lib.make_params(lattice, dims, 0.8, storage, force_field=True)
     expect_f = 2 * up(Q * P * sbytes) + up(D * N * abytes) + up(512 * Q * 8) + up(64)
     assert _lib.workspace_bytes(pf) == expect_f
+    # plates: wall densities per (x, z) column and plate, emission tables
+    pw = _lib.make_params(lattice, dims, 0.8, storage, walls=True)
+    expect_w = expect + up(2 * dims[0] * dims[2] * 8) + up(2 * (Q + 1) * 8)
+    assert _lib.workspace_bytes(pw) == expect_w
 
 
 def test_null_handle_calls(lib):
@@ -160,6 +164,7 @@ def test_null_handle_calls(lib):
     assert lib.lbm_set_block(None, 64) == _lib.LBM_EINVAL
     assert lib.lbm_set_stream(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_set_viscosity(None, 0.1) == _lib.LBM_EINVAL
+    assert lib.lbm_set_walls(None, 1, 1.0, 1.0, 0.0, 0.0) == _lib.LBM_EINVAL
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_population_bytes(None) == 0
     assert lib.lbm_lattice_table(5, None, None, None) == _lib.LBM_EINVAL
