@@ -127,9 +127,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
         fh.write("# HBM traffic of the fused step kernel, D3Q39 FP32 (deviation storage), 256^3 Kolmogorov\n")
         fh.write("# counter runs (repo root, MI355X), one counter per run:\n")
         fh.write("#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python3 bench.py "
-                 "--steps 5 --warmup 2 --cpu-steps 0 --copy-calib\n")
+                 "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n")
         fh.write("#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python3 bench.py "
-                 "--steps 5 --warmup 2 --cpu-steps 0 --copy-calib\n")
+                 "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n")
         fh.write("# summarised by:\n#   python3 bench.py --summarize-pmc "
                  "gpurun_out/pmc_fetch/pmc_counter_collection.csv "
                  "gpurun_out/pmc_write/pmc_counter_collection.csv\n")
