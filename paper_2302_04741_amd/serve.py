@@ -108,8 +108,10 @@ def request_bytes(req: Request, storage: str) -> int:
     """HBM a request holds while admitted: its workspace."""
     from . import _lib
 
-    p = _lib.make_params(req.workload.lattice, req.workload.dims, req.workload.tau_hat, storage,
-                         req.workload.eq_order, req.workload.force_order)
+    wl = req.workload
+    # the same flags sim.from_workload creates the handle with
+    p = _lib.make_params(wl.lattice, wl.dims, wl.tau_hat, storage, wl.eq_order, wl.force_order,
+                         force_field=wl.force[0] == "field", walls=wl.walls is not None)
     return _lib.workspace_bytes(p) + 256
 
 

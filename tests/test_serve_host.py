@@ -42,3 +42,17 @@ def test_admission_by_slots_and_budget():
     assert not a.fits(1)  # slots
     with pytest.raises(AssertionError):
         a.take(1)
+
+
+def test_request_bytes_is_the_workspace_of_the_handle():
+    from paper_2302_04741_amd import _lib, workloads
+
+    r = serve.make_requests(n=1, seed=2)[0]
+    p = _lib.make_params(r.workload.lattice, r.workload.dims, r.workload.tau_hat, "f32")
+    assert serve.request_bytes(r, "f32") == _lib.workspace_bytes(p) + 256
+    # a full force field and plates need more workspace, and are budgeted for
+    wl = workloads.random_smooth("D2Q37", (64, 40, 1), seed=1, force_kind="field")
+    wl.walls = (1.0, 1.1, 0.0, 0.0)
+    big = serve.Request(0, 0.0, wl, 10)
+    pf = _lib.make_params("D2Q37", (64, 40, 1), wl.tau_hat, "f32", force_field=True, walls=True)
+    assert serve.request_bytes(big, "f32") == _lib.workspace_bytes(pf) + 256
