@@ -151,7 +151,18 @@ def cpu_baseline(wl, steps: int):
     return {"value": wl.ncell * steps / dt / 1e6, "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "FP64 oracle, full %dx%dx%d grid of the same workload, %d steps "
-                      "(%.1f s, init excluded)" % (*wl.dims, steps, dt)}
+                      "(%.1f s, init excluded), %s" % (*wl.dims, steps, dt, _cpu_model())}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def _grid_mix(kind: str, count: int, seed: int):
@@ -295,6 +306,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (default 256)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
+    ap.add_argument("--tau", type=float, default=0.8, help="tau-hat of the step workload")
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed regions of --steps steps reported as a spread")
@@ -349,7 +361,7 @@ def main(argv=None) -> int:
     from paper_2302_04741_amd import sim as lbm_sim
     from paper_2302_04741_amd import workloads
 
-    wl = workloads.kolmogorov_3d(n=args.n)
+    wl = workloads.kolmogorov_3d(n=args.n, tau_hat=args.tau)
     s = lbm_sim.from_workload(wl, storage=args.storage)
     if args.block:
         s.set_block(args.block)
@@ -414,9 +426,9 @@ def main(argv=None) -> int:
         "dtype": {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}[args.storage],
         "data": "synthetic",
         "config": {
-            "workload": "D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=0.8, "
+            "workload": "D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=%g, "
                         "3rd-order equilibrium, force with a3_F and sigma"
-                        % (args.n, args.storage.upper()),
+                        % (args.n, args.storage.upper(), args.tau),
             "grid": [args.n] * 3,
             "storage": args.storage,
             "block": args.block or "default",
