@@ -234,3 +234,23 @@ def test_batch_and_graph_argument_checks(lib):
     lib.lbm_batch_destroy(h)
     lib.lbm_batch_destroy(None)
     lib.lbm_graph_destroy(None)
+
+
+@pytest.mark.parametrize("storage,sbytes", [("f32", 4), ("f64", 8), ("f16dev", 2)])
+def test_largest_plane(lib, storage, sbytes):
+    """One population plane (rows padded to 64 values) must stay below 4 GiB so
+    that 32-bit byte offsets address it: the largest accepted grids and the
+    first refused ones, including a grid refused only because of the padding."""
+    cap = (1 << 32) // sbytes  # values per plane at the limit
+    ny = 1024
+    nz = cap // (1024 * ny)     # nx = 1024: plane exactly at the limit
+    ok = params(lattice="D3Q39", dims=(1024, ny, nz - 1), storage=storage)
+    assert _lib.workspace_bytes(ok) > 2 * 39 * 1024 * ny * (nz - 1) * sbytes
+    at = params(lattice="D3Q39", dims=(1024, ny, nz), storage=storage)
+    assert _lib.workspace_bytes(at) == 0
+    st, _ = create(lib, at, nbytes=1 << 40)
+    assert st == _lib.LBM_EUNSUPPORTED
+    # 1000 values per row are stored as 1024: refused although 1000*ny*nz fits
+    padded = params(lattice="D3Q39", dims=(1000, ny, nz), storage=storage)
+    assert 1000 * ny * nz * sbytes < (1 << 32)
+    assert _lib.workspace_bytes(padded) == 0
