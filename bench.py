@@ -325,7 +325,7 @@ def main(argv=None) -> int:
                     help="batch: number of grids (default 64); serve: requests (default 256)")
     ap.add_argument("--seed", type=int, default=4741)
     ap.add_argument("--batch-threads", type=int, default=0,
-                    help="batch: tile width / threads per block (64, 128, 256; 0 = 256)")
+                    help="batch: threads per block (64, 128, 256; 0 = 128)")
     ap.add_argument("--batch-blocks", type=int, default=0,
                     help="batch: 0 = one block per tile, > 0 = persistent grid")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")

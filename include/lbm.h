@@ -185,8 +185,10 @@ LBM_API lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
 /* Change the stream of a handle (work already queued stays where it is). */
 LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
 
-/* Kernel launch shape of the step: threads per block along x (64, 128, 256,
- * 512 or 1024).  0 restores the default.  Results do not depend on it. */
+/* Kernel launch shape of the step: threads per block (64, 128, 256, 512 or
+ * 1024; FP64 storage uses at most 256), i.e. wavefronts per block, each
+ * wavefront updating 64 consecutive cells of one row.  0 restores the default
+ * (1024 for FP32 storage, 256 for FP64 and F16).  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
 /* Relaxation time per cell (Sec. 3 of the paper: tau = mu/(rho theta) keeps the
@@ -230,9 +232,10 @@ LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
 
 /* A batch advances its member simulations together: every step is ONE launch
  * of a multi-grid kernel over a list of tiles spanning all members (one tile =
- * a run of `threads` cells along x in one grid row of one member).  By default
- * each tile is one block and the hardware balances uneven members; with a
- * block count set, a persistent grid walks the list with a fixed stride.
+ * 64 consecutive cells of one grid row of one member, updated by one
+ * wavefront).  By default every tile gets its own wavefront and the hardware
+ * balances uneven members; with a block count set, a persistent grid walks the
+ * list with a fixed stride.
  * Members must share lattice, storage, eq_order and force_order; grid sizes,
  * tau_hat, mu, rho0 and forces may differ.  The per-cell arithmetic is that of
  * lbm_step, so a member's result does not depend on the other members or on
@@ -249,12 +252,11 @@ LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t cou
 /* Advance every member by nsteps (>= 0) steps, one launch per step. */
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
-/* Launch shape of the multi-grid kernel.  threads: tile width and threads per
- * block, 64, 128 or 256 (0 = 256); blocks: 0 = one block per tile (default),
- * > 0 = a persistent grid of that many blocks (at most 2^31 - 1).  A new tile
- * width rebuilds the tile table from the members' current state (LBM_EINVAL,
- * and the batch must be set again, if a member went stale).  Graphs captured
- * before must be captured again. */
+/* Launch shape of the multi-grid kernel.  threads: threads per block, 64, 128
+ * or 256 (0 = 128), i.e. 1, 2 or 4 tiles per block; blocks: 0 = enough blocks
+ * for one wavefront per tile (default), > 0 = a persistent grid of that many
+ * blocks (at most 2^31 - 1).  Results do not depend on the shape.  Graphs
+ * captured before must be captured again. */
 LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks);
 
 /* NULL-safe; does not free the workspace.  Waits only for the last tile-table

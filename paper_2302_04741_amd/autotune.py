@@ -2,8 +2,8 @@
 
 * Single-grid step: threads per block (64 ... 1024) per (lattice, storage,
   equilibrium order, force order, grid class).
-* Multi-grid (batched) step: tile width and grid (one block per tile or a
-  persistent grid) per (lattice, storage, orders, batch class).
+* Multi-grid (batched) step: threads per block and grid (one wavefront per
+  tile or a persistent grid) per (lattice, storage, orders, batch class).
 
 Candidates are timed with HIP events on scratch simulations of the same shape
 (smooth synthetic fields; the cost of a step does not depend on the data), so
@@ -18,7 +18,7 @@ import os
 import threading
 
 BLOCK_CANDIDATES = (64, 128, 256, 512, 1024)
-# (threads per block = tile width, blocks: 0 = one per tile, else persistent)
+# (threads per block, blocks: 0 = one wavefront per tile, else a persistent grid)
 BATCH_CANDIDATES = ((64, 0), (128, 0), (256, 0), (256, 1280), (256, 2560), (64, 5120))
 
 _lock = threading.Lock()

@@ -514,7 +514,7 @@ struct lbm_batch {
     int64_t generation;                // bumped whenever the table or launch shape changes
     int64_t steps_done;                // batch steps since the table was built
     int64_t ntiles;
-    int threads;     // tile width and block size
+    int threads;     // threads per block (tiles of 64 cells, one per wavefront)
     int64_t blocks;  // 0: one block per tile
     bool upload_pending;  // an asynchronous upload may still read `host`
 };
@@ -532,7 +532,7 @@ struct lbm_graph {
 };
 
 namespace {
-constexpr int BATCH_DEFAULT_THREADS = 256;
+constexpr int BATCH_DEFAULT_THREADS = 128;  // measured best on the serving and small-grid mixes
 
 size_t batch_begin_bytes(int32_t max_sims) { return align_up(size_t(max_sims + 1) * 8); }
 
@@ -563,7 +563,7 @@ lbm_status batch_launch(lbm_batch *b, int64_t nsteps)
     return LBM_OK;
 }
 
-// Build the tile table of `sims` for the batch's tile width and upload it on
+// Build the tile table of `sims` (64-cell tiles) and upload it on
 // the batch's stream (the host staging copy lives in the batch, so the
 // asynchronous copy never reads freed memory).
 lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
@@ -588,7 +588,7 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
         t.pop[0] = s->pop[0];
         t.pop[1] = s->pop[1];
         t.cur = s->cur;
-        t.chunks_x = int32_t((s->p.nx + b->threads - 1) / b->threads);
+        t.chunks_x = int32_t((s->p.nx + 63) / 64);
         t.tile_begin = tiles;
         t.gd = s->gd;
         t.fd = s->fd;
@@ -700,22 +700,10 @@ lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks)
         return fail(LBM_EINVAL, "threads must be 0, 64, 128 or 256 (got %d)", threads);
     if (blocks < 0 || blocks > 0x7fffffff)
         return fail(LBM_EINVAL, "blocks must be in [0, 2^31 - 1]");
-    const int th = threads ? threads : BATCH_DEFAULT_THREADS;
+    // the tiles do not depend on the launch shape: the table stays as it is
+    b->threads = threads ? threads : BATCH_DEFAULT_THREADS;
     b->blocks = blocks;
-    b->generation++;
-    if (th != b->threads) {
-        b->threads = th;
-        if (!b->sims.empty()) {
-            // the tiles change with their width: rebuild from the members' state
-            if (batch_check(b) != LBM_OK) {
-                b->sims.clear();
-                return fail(LBM_EINVAL, "members went stale; call lbm_batch_set");
-            }
-            std::vector<lbm_sim *> members(b->sims);
-            lbm_status st = batch_build(b, members.data(), int32_t(members.size()));
-            if (st != LBM_OK) return st;
-        }
-    }
+    b->generation++;  // graphs captured with the old shape are stale
     return ok();
 }
 

@@ -182,11 +182,12 @@ struct StepCoef {
 };
 
 // One member of a multi-grid batch (device table entry).  Its tiles are runs
-// of blockDim.x cells along x: chunks_x per grid row, rows in (z, y) order.
+// of 64 cells along x (one wavefront each): chunks_x per grid row, rows in
+// (z, y) order.
 struct TileSim {
     const void *pop[2];  // the two population buffers
     int32_t cur;         // buffer holding the state when the table was built
-    int32_t chunks_x;    // tiles per grid row, ceil(nx / tile width)
+    int32_t chunks_x;    // tiles per grid row, ceil(nx / 64)
     int64_t tile_begin;  // first tile of this simulation in the list
     GridDims gd;
     ForceDesc fd;
@@ -548,7 +549,7 @@ struct BatchLaunch {
     int nsims;
     int64_t ntiles;         // tiles of all members
     int parity;             // batch steps since the table was built, mod 2
-    int threads;            // tile width = threads per block (64, 128 or 256)
+    int threads;            // threads per block (64, 128 or 256): 1, 2 or 4 tiles
     int64_t blocks;         // 0: one block per tile; > 0: persistent walk
     hipStream_t stream;
 };

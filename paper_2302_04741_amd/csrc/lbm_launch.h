@@ -37,11 +37,15 @@ template <int LAT, class S>
 hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                           const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
 {
-    int bx = block_for(gd, lc.block);
+    // blocks of bx/64 wavefronts, one wavefront per 64 cells of a row
+    int bx = lc.block > 0 ? lc.block : step_default_threads<S>();
     bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
+    const int64_t waves = ((int64_t(gd.nx) + 63) / 64) * gd.ny * gd.nz;
+    const int64_t wpb = bx / 64;
+    const dim3 grid(unsigned((waves + wpb - 1) / wpb));
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
-        hipLaunchKernelGGL((step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
-                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, static_cast<const S *>(A),
+        hipLaunchKernelGGL((step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>), grid,
+                           dim3(bx), 0, lc.stream, static_cast<const S *>(A),
                            static_cast<S *>(B), gd, fd, co);
         return hipGetLastError();
     });
@@ -51,9 +55,11 @@ template <int LAT, class S>
 hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl)
 {
     if (bl.ntiles <= 0) return hipSuccess;
-    // one block per tile, or the persistent grid; the kernel strides over the
-    // list, so a grid capped at 2^31 - 1 blocks still covers every tile
-    int64_t grid = bl.blocks > 0 ? std::min(bl.blocks, bl.ntiles) : bl.ntiles;
+    // one wavefront per tile, or the persistent grid; the kernel strides over
+    // the list, so a grid capped at 2^31 - 1 blocks still covers every tile
+    const int64_t wpb = bl.threads / 64;
+    const int64_t need = (bl.ntiles + wpb - 1) / wpb;
+    int64_t grid = bl.blocks > 0 ? std::min(bl.blocks, need) : need;
     grid = std::min<int64_t>(grid, 0x7fffffff);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((multi_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),

@@ -346,8 +346,8 @@ class Batch:
         self._post()
 
     def set_launch(self, threads: int = 0, blocks: int = 0):
-        """Tile width / threads per block (64, 128, 256; 0 = 256) and grid
-        (0 = one block per tile, > 0 = persistent grid of that many blocks)."""
+        """Threads per block (64, 128, 256; 0 = 128) and grid (0 = one
+        wavefront per 64-cell tile, > 0 = persistent grid of that many blocks)."""
         check(load().lbm_batch_set_launch(self.handle, int(threads), int(blocks)))
 
     def close(self):

@@ -67,7 +67,7 @@ def test_batch_member_independent_of_mix_bitwise(sim_mod, lattice, storage):
         assert torch.equal(s.get_populations().cpu(), ref)
 
 
-# (threads = tile width, blocks: 0 = one block per tile, else a persistent grid)
+# (threads per block, blocks: 0 = one wavefront per tile, else a persistent grid)
 LAUNCHES = [(256, 0), (64, 0), (128, 0), (256, 3), (64, 1000)]
 
 
@@ -88,7 +88,7 @@ def test_batch_launch_shapes_bitwise(sim_mod, lattice, storage):
     for k in range(1, len(LAUNCHES)):
         for a, c in zip(out[0], out[k]):
             assert torch.equal(a, c), LAUNCHES[k]
-    # a new tile width between steps rebuilds the table from the current state
+    # a new launch shape between steps continues from the current state
     sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
     b = sim_mod.Batch(len(sims))
     b.set(sims)
