@@ -114,12 +114,13 @@ template <class S> constexpr int step_max_threads()
     return sizeof(typename ArithOf<S>::type) == 8 ? 256 : 1024;
 }
 
-// Default block of the step (measured on the 256^3, 384^3 and 640^3 D3Q39
-// workloads): 16 wavefronts for FP32 storage (+2% over 4), 4 for F16 (larger
-// blocks lose 5%) and FP64 (the most that fits).
-template <class S> constexpr int step_default_threads()
+// Default block of the step, measured: 4 wavefronts, except 16 for D3Q39 FP32
+// storage on grids of at least 2^17 wavefronts (256^3: +2%, 384^3: +2%; on
+// smaller D3Q39 grids and on every D2Q37 grid 16-wavefront blocks lose 5-20%,
+// F16 storage loses 5% with them and FP64 cannot use them).
+template <int LAT, class S> inline int step_default_threads(int64_t waves)
 {
-    return sizeof(S) == 4 ? 1024 : 256;
+    return (LAT == 1 && sizeof(S) == 4 && waves >= (int64_t(1) << 17)) ? 1024 : 256;
 }
 
 // The fused update of one cell (x, y, z): gather, moments, equilibrium, stress,

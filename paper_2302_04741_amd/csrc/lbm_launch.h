@@ -38,9 +38,9 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
                           const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
 {
     // blocks of bx/64 wavefronts, one wavefront per 64 cells of a row
-    int bx = lc.block > 0 ? lc.block : step_default_threads<S>();
-    bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
     const int64_t waves = ((int64_t(gd.nx) + 63) / 64) * gd.ny * gd.nz;
+    int bx = lc.block > 0 ? lc.block : step_default_threads<LAT, S>(waves);
+    bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
     const int64_t wpb = bx / 64;
     const dim3 grid(unsigned((waves + wpb - 1) / wpb));
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
