@@ -188,8 +188,8 @@ LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
 /* Kernel launch shape of the step: threads per block (64, 128, 256, 512 or
  * 1024; FP64 storage uses at most 256), i.e. wavefronts per block, each
  * wavefront updating 64 consecutive cells of one row.  0 restores the default
- * (256; 1024 for D3Q39 FP32 grids of at least 2^17 wavefronts).  Results do not
- * depend on it. */
+ * (256; 128 for FP64 storage; 1024 for D3Q39 FP32 grids of at least 2^17
+ * wavefronts).  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
 /* Relaxation time per cell (Sec. 3 of the paper: tau = mu/(rho theta) keeps the

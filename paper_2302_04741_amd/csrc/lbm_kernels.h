@@ -117,9 +117,11 @@ template <class S> constexpr int step_max_threads()
 // Default block of the step, measured: 4 wavefronts, except 16 for D3Q39 FP32
 // storage on grids of at least 2^17 wavefronts (256^3: +2%, 384^3: +2%; on
 // smaller D3Q39 grids and on every D2Q37 grid 16-wavefront blocks lose 5-20%,
-// F16 storage loses 5% with them and FP64 cannot use them).
+// F16 storage loses 5% with them) and 2 for FP64 storage (D3Q39 256^3: +6%,
+// D2Q37 1024^2: +4% over 4; FP64 cannot use more than 4).
 template <int LAT, class S> inline int step_default_threads(int64_t waves)
 {
+    if (sizeof(S) == 8) return 128;
     return (LAT == 1 && sizeof(S) == 4 && waves >= (int64_t(1) << 17)) ? 1024 : 256;
 }
 
