@@ -250,7 +250,11 @@ LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t wo
  * Destroying a member leaves the batch unusable until the next lbm_batch_set. */
 LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count);
 
-/* Advance every member by nsteps (>= 0) steps, one launch per step. */
+/* Advance every member by nsteps (>= 0) steps, one launch per step, on the
+ * batch's stream.  The library does not order that stream with the members'
+ * own streams: work queued on a member's stream must be complete (or ordered
+ * with events) before, and later work on it must wait for the batch's stream
+ * (the Python binding does both). */
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
 /* Launch shape of the multi-grid kernel.  threads: threads per block, 64, 128
