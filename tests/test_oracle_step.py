@@ -8,6 +8,8 @@
   eq. (lbm)).
 * Shear-wave decay at nu = (tau-hat - 1/2) theta (tau = tau-hat - 1/2, Sec. 2),
   with second-order convergence of the lattice error.
+* Isobaric temperature wave (the entropy mode) decaying at the thermal
+  diffusivity lambda/(rho c_p) = nu: BGK has Prandtl number 1.
 * Mid-point stress sigma-bar against the Newtonian stress of the Chapman-Enskog
   estimate (Sec. 2): sigma = mu (grad u + grad u^T - (2/D) div u delta).
 * The paper's central claim (abstract, Sec. 2): dropping the third-moment force
@@ -285,3 +287,37 @@ def test_viscosity_mode_q_err(oracle_mod, lat):
         rho, u, theta = sim.moments()
     ref = q_err_printed(D, rho[0], u[:, 0], theta[0], g, mu / (rho[0] * theta[0]))
     np.testing.assert_allclose(q[2] - q[4], ref, rtol=1e-4, atol=0)
+
+
+def temperature_wave_rate(oracle_mod, lat, L, tau_hat):
+    """Decay rate of theta = 1 + eps sin(2 pi y/L) at uniform pressure (rho =
+    1/theta, u = 0), from a least-squares fit of log(amplitude) over one e-fold
+    of the expected decay (averages out the weak sound waves of the start)."""
+    D = oracle_mod.DIM[lat]
+    r = oracle_mod.lattice(lat)[2]
+    y = np.arange(L)
+    s = np.sin(2 * np.pi * y / L)
+    theta = 1 + 1e-4 * s
+    sim = oracle_mod.OracleSim(lat, (1, L, 1), tau_hat, 1 / theta, np.zeros((D, L)), theta,
+                               np.zeros(D))
+    k = 2 * np.pi / L / r
+    e_fold = 1 / ((tau_hat - 0.5) * k * k)
+    n0, n1 = int(0.3 * e_fold), int(1.3 * e_fold)
+    ts, amps = [], []
+    for n in range(n0, n1, max(1, (n1 - n0) // 100)):
+        sim.step(n - sim.time)
+        th = sim.moments()[2]
+        ts.append(n)
+        amps.append(2.0 / L * ((th - 1) * s).sum())
+    return -np.polyfit(ts, np.log(amps), 1)[0], k
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_temperature_wave_decays_at_nu(oracle_mod, lat):
+    tau_hat = 0.8
+    errs = []
+    for L in (32, 64):
+        rate, k = temperature_wave_rate(oracle_mod, lat, L, tau_hat)
+        errs.append(abs(rate / ((tau_hat - 0.5) * k * k) - 1))
+    assert errs[1] < 4e-3
+    assert errs[1] < errs[0]  # the lattice error shrinks with the wavelength
