@@ -10,6 +10,9 @@
   with second-order convergence of the lattice error.
 * Isobaric temperature wave (the entropy mode) decaying at the thermal
   diffusivity lambda/(rho c_p) = nu: BGK has Prandtl number 1.
+* Isentropic standing sound wave oscillating at the adiabatic speed of sound
+  sqrt(gamma theta), gamma = (D + 2)/D (an isothermal model would give
+  sqrt(theta)), with second-order convergence of the lattice error.
 * Mid-point stress sigma-bar against the Newtonian stress of the Chapman-Enskog
   estimate (Sec. 2): sigma = mu (grad u + grad u^T - (2/D) div u delta).
 * The paper's central claim (abstract, Sec. 2): dropping the third-moment force
@@ -321,3 +324,33 @@ def test_temperature_wave_decays_at_nu(oracle_mod, lat):
         errs.append(abs(rate / ((tau_hat - 0.5) * k * k) - 1))
     assert errs[1] < 4e-3
     assert errs[1] < errs[0]  # the lattice error shrinks with the wavelength
+
+
+def sound_frequency_ratio(oracle_mod, lat, L):
+    """omega / (c_s k) of an isentropic standing wave (rho and theta in phase,
+    delta theta/theta = (gamma - 1) delta rho/rho, u = 0), from the zero
+    crossings of the density amplitude over four periods."""
+    D = oracle_mod.DIM[lat]
+    r = oracle_mod.lattice(lat)[2]
+    gamma = (D + 2) / D
+    y = np.arange(L)
+    s = np.sin(2 * np.pi * y / L)
+    rho = 1 + 1e-4 * s
+    theta = 1 + (gamma - 1) * 1e-4 * s
+    sim = oracle_mod.OracleSim(lat, (1, L, 1), 0.8, rho, np.zeros((D, L)), theta, np.zeros(D))
+    k = 2 * np.pi / L / r
+    period = 2 * np.pi / (np.sqrt(gamma) * k)
+    a = []
+    for _ in range(int(4 * period) + 2):
+        a.append(2.0 / L * ((sim.moments()[0] - 1) * s).sum())
+        sim.step(1)
+    zc = [i + a[i] / (a[i] - a[i + 1]) for i in range(len(a) - 1) if a[i] * a[i + 1] < 0]
+    return period / (2 * np.mean(np.diff(zc)))
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_sound_speed_is_adiabatic(oracle_mod, lat):
+    e32 = abs(sound_frequency_ratio(oracle_mod, lat, 32) - 1)
+    e64 = abs(sound_frequency_ratio(oracle_mod, lat, 64) - 1)
+    assert e64 < 3e-4
+    assert 3.0 < e32 / e64 < 5.0  # O(k^2)
