@@ -123,16 +123,17 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
         "write_over_algorithmic": round(write_b / (alg / 2), 4),
         "dispatches_averaged": "%d fetch, %d write" % (nf, nw),
     }
+    # the counter runs wrote their CSV files as <dir>/pmc_counter_collection.csv
+    dirs = [os.path.relpath(os.path.dirname(os.path.abspath(p)), ROOT)
+            for p in (fetch_csv, write_csv)]
     with open(out_path, "w") as fh:
         fh.write("# HBM traffic of the fused step kernel, D3Q39 FP32 (deviation storage), 256^3 Kolmogorov\n")
         fh.write("# counter runs (repo root, MI355X), one counter per run:\n")
-        fh.write("#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python3 bench.py "
-                 "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n")
-        fh.write("#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python3 bench.py "
-                 "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n")
-        fh.write("# summarised by:\n#   python3 bench.py --summarize-pmc "
-                 "gpurun_out/pmc_fetch/pmc_counter_collection.csv "
-                 "gpurun_out/pmc_write/pmc_counter_collection.csv\n")
+        for counter, d in zip(("FETCH_SIZE", "WRITE_SIZE"), dirs):
+            fh.write("#   rocprofv3 --pmc %s -f csv -d %s -o pmc -- python3 bench.py "
+                     "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n" % (counter, d))
+        fh.write("# summarised by:\n#   python3 bench.py --summarize-pmc %s %s\n"
+                 % tuple(os.path.relpath(os.path.abspath(p), ROOT) for p in (fetch_csv, write_csv)))
         fh.write("# scale = 2 GiB / counter value of the 2 GiB plain device copy in the same run\n")
         for k, v in out.items():
             fh.write("%s: %s\n" % (k, v))

@@ -55,7 +55,7 @@ typedef struct lbm_sim lbm_sim; /* opaque host handle */
 typedef enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad value) */
-    LBM_EUNSUPPORTED = -2, /* valid request this build does not implement */
+    LBM_EUNSUPPORTED = -2, /* valid request the library does not implement */
     LBM_EDEVICE = -3,      /* a HIP call failed; see lbm_last_error() */
     LBM_ENOSPACE = -4,     /* workspace too small */
     LBM_ENONFINITE = -5    /* a global total is NaN or infinite (diverged run) */
