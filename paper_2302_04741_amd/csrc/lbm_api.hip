@@ -4,6 +4,7 @@
 // handle's stream.  The library allocates no device memory: every buffer is a
 // slice of the caller's workspace.  Argument checks run before any HIP call,
 // so they also work on a machine without a GPU.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -37,8 +38,10 @@ struct lbm_sim {
     int block;
     int64_t gen;  // bumped when launch arguments change (force, block, stream, plates)
     WallDesc wd;  // plates (off unless lbm_set_walls)
-    double *wall_rw;
-    double *wall_e;
+    int64_t resident_max;  // grids of at most this many cells step in one workgroup
+    double *wall_part;     // plates: partial sums of the crossing slots, per buffer
+    double *wall_e;        // plates: emission tables
+    bool wall_fresh;       // plates: wall_part holds the sums of the current state
 };
 
 namespace {
@@ -104,9 +107,9 @@ Layout layout_of(const lbm_params *p)
     L.off_gtab = 2 * L.pop;
     L.off_part = L.off_gtab + L.gtab;
     L.off_tot = L.off_part + L.partials;
-    // plates: wall densities [2][nx*nz], emission tables [2][Q + 1]
+    // plates: partial sums [2 buffer][2 plate][3 row][nx*nz], emission tables [2][Q + 1]
     L.walls = (p->flags & LBM_FLAG_WALLS)
-                  ? align_up(2 * size_t(p->nx) * size_t(p->nz) * sizeof(double)) +
+                  ? align_up(12 * size_t(p->nx) * size_t(p->nz) * sizeof(double)) +
                         align_up(2 * size_t(Q + 1) * sizeof(double))
                   : 0;
     L.off_walls = L.off_tot + L.totals;
@@ -151,31 +154,77 @@ lbm_status check_params(const lbm_params *p)
     return LBM_OK;
 }
 
-LaunchCfg cfg(const lbm_sim *s) { return LaunchCfg{s->block, s->stream, s->wd}; }
-
-// With plates, the wall densities of the current state come first.
-hipError_t wall_densities(const lbm_sim *s)
+// Launch settings for a kernel reading the state in pop[cur] (with plates, the
+// partial sums of that buffer).
+LaunchCfg cfg(const lbm_sim *s, int cur)
 {
-    if (!s->wd.on) return hipSuccess;
-    return launch_wall_mass(s->p.lattice, s->p.storage, s->pop[s->cur], s->gd, s->co, cfg(s));
+    LaunchCfg c{s->block, s->stream, s->wd};
+    c.walls.par = cur;
+    return c;
+}
+LaunchCfg cfg(const lbm_sim *s) { return cfg(s, s->cur); }
+
+// The resident kernel is opt-in (lbm_set_resident_limit): one CU computing
+// every cell costs about as much per step as a launch over the whole chip, so
+// it gains little (at most ~15%, grids below ~300 cells) and loses above.
+constexpr int64_t RESIDENT_DEFAULT_MAX_CELLS = 0;
+constexpr int64_t RESIDENT_MAX_STEPS_PER_LAUNCH = 4096;
+
+// With plates, whatever reads the state needs the partial sums of the current
+// state: steps keep them (each writes those of the state it produces); after
+// the state was written otherwise (initialisation, lbm_set_populations) one
+// pass over the columns computes them.
+hipError_t wall_densities(lbm_sim *s)
+{
+    if (!s->wd.on || s->wall_fresh) return hipSuccess;
+    hipError_t e =
+        launch_wall_mass(s->p.lattice, s->p.storage, s->pop[s->cur], s->gd, s->co, cfg(s));
+    s->wall_fresh = e == hipSuccess;
+    return e;
 }
 
-// One time step: K1 over every row, then, with plates, the rows next to them
-// again with the plates' emission (their densities taken from the same state).
+bool resident(const lbm_sim *s) { return s->N <= s->resident_max; }
+
+// One time step, one launch: K1, or with plates K1c (which also writes the
+// partial sums of the state it produces).
 hipError_t launch_one_step(const lbm_sim *s, int cur)
 {
     const void *A = s->pop[cur];
     void *B = s->pop[cur ^ 1];
-    hipError_t e;
-    if (s->wd.on) {
-        e = launch_wall_mass(s->p.lattice, s->p.storage, A, s->gd, s->co, cfg(s));
-        if (e != hipSuccess) return e;
+    if (s->wd.on)
+        return launch_wall_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B,
+                                s->gd, s->fd, s->co, cfg(s, cur));
+    return launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B, s->gd, s->fd,
+                       s->co, cfg(s, cur));
+}
+
+// Enqueues nsteps steps of the state held in pop[cur] (with plates, its partial
+// sums must be current); on return cur names the buffer holding the advanced
+// state and done the steps enqueued (all of them unless a launch failed).  Small grids take the resident kernel, many steps
+// per launch in chunks that keep every launch short; the others one launch (or
+// three, with plates) per step.
+hipError_t launch_steps(const lbm_sim *s, int &cur, int64_t nsteps, int64_t &done)
+{
+    done = 0;
+    if (resident(s)) {
+        while (done < nsteps) {
+            const int k = int(std::min<int64_t>(nsteps - done, RESIDENT_MAX_STEPS_PER_LAUNCH));
+            hipError_t e = launch_resident(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
+                                           s->pop[cur], s->pop[cur ^ 1], s->gd, s->fd, s->co,
+                                           cfg(s, cur), k);
+            if (e != hipSuccess) return e;
+            cur ^= (k & 1);
+            done += k;
+        }
+        return hipSuccess;
     }
-    e = launch_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B, s->gd, s->fd,
-                    s->co, cfg(s));
-    if (e != hipSuccess || !s->wd.on) return e;
-    return launch_wall_step(s->p.lattice, s->p.storage, s->eq, s->p.force_order, A, B, s->gd,
-                            s->fd, s->co, cfg(s));
+    while (done < nsteps) {
+        hipError_t e = launch_one_step(s, cur);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+        done++;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -227,15 +276,17 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->partials = reinterpret_cast<double *>(s->ws + L.off_part);
     s->totals_dev = reinterpret_cast<double *>(s->ws + L.off_tot);
     s->wd = WallDesc{0, 0, nullptr, nullptr};
-    s->wall_rw = nullptr;
+    s->wall_part = nullptr;
     s->wall_e = nullptr;
+    s->wall_fresh = false;
     if (p->flags & LBM_FLAG_WALLS) {
-        s->wall_rw = reinterpret_cast<double *>(s->ws + L.off_walls);
+        s->wall_part = reinterpret_cast<double *>(s->ws + L.off_walls);
         s->wall_e = reinterpret_cast<double *>(
-            s->ws + L.off_walls + align_up(2 * size_t(p->nx) * size_t(p->nz) * sizeof(double)));
+            s->ws + L.off_walls + align_up(12 * size_t(p->nx) * size_t(p->nz) * sizeof(double)));
     }
     s->step = 0;
     s->block = 0;
+    s->resident_max = RESIDENT_DEFAULT_MAX_CELLS;
     hipError_t e = launch_init(p->lattice, p->storage, s->eq, p->force_order, rho, u, theta,
                                s->pop[0], s->gd, s->fd, s->co, cfg(s));
     if (e != hipSuccess) {
@@ -309,6 +360,7 @@ lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis
         e = launch_init(s->p.lattice, s->p.storage, s->eq, s->p.force_order, mrho, mu, mth,
                         s->pop[s->cur], s->gd, s->fd, s->co, cfg(s));
         if (e != hipSuccess) return dev_fail(e, "init kernel launch");
+        s->wall_fresh = false;
     }
     return ok();
 }
@@ -317,11 +369,17 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_one_step(s, s->cur);
-        if (e != hipSuccess) return dev_fail(e, "step kernel launch");
-        s->cur ^= 1;
-        s->step++;
+    if (nsteps == 0) return ok();
+    hipError_t e = wall_densities(s);
+    if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
+    int cur = s->cur;
+    int64_t done = 0;
+    e = launch_steps(s, cur, nsteps, done);
+    s->cur = cur;
+    s->step += done;
+    if (e != hipSuccess) {
+        s->wall_fresh = false;
+        return dev_fail(e, "step kernel launch");
     }
     return ok();
 }
@@ -400,6 +458,7 @@ lbm_status lbm_set_populations(lbm_sim *s, const void *src)
                                     size_t(s->gd.nx) * sb, size_t(s->gd.nx) * sb,
                                     size_t(s->Q) * size_t(s->gd.ny) * size_t(s->gd.nz),
                                     hipMemcpyDeviceToDevice, s->stream);
+    s->wall_fresh = false;
     if (e != hipSuccess) return dev_fail(e, "population copy");
     return ok();
 }
@@ -443,6 +502,15 @@ lbm_status lbm_set_viscosity(lbm_sim *s, double mu)
     return ok();
 }
 
+lbm_status lbm_set_resident_limit(lbm_sim *s, int64_t max_cells)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (max_cells < 0) return fail(LBM_EINVAL, "max_cells must be >= 0");
+    s->resident_max = max_cells;
+    s->gen++;
+    return ok();
+}
+
 lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double theta_t, double u_b,
                          double u_t)
 {
@@ -468,11 +536,12 @@ lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double thet
         const double th[2] = {theta_b, theta_t}, uw[2] = {u_b, u_t};
         e = launch_wall_setup(s->p.lattice, s->eq, th, uw, s->p.ny, s->wall_e, s->stream);
         if (e != hipSuccess) return dev_fail(e, "plate setup kernel launch");
-        s->wd = WallDesc{1, 0, s->wall_rw, s->wall_e};
+        s->wd = WallDesc{1, 0, s->wall_part, s->wall_e};
     } else {
         s->wd = WallDesc{0, 0, nullptr, nullptr};
     }
     s->gen++;
+    s->wall_fresh = false;
     e = launch_init(s->p.lattice, s->p.storage, s->eq, s->p.force_order, mrho, mu, mth,
                     s->pop[s->cur], s->gd, s->fd, s->co, cfg(s));
     if (e != hipSuccess) return dev_fail(e, "init kernel launch");
@@ -742,20 +811,22 @@ lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph 
     g->gen = s ? s->gen : b->generation;
     g->cur0 = s ? s->cur : 0;
     g->parity0 = b ? int32_t(b->steps_done & 1) : 0;
-    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = s ? wall_densities(s) : hipSuccess;  // not part of the capture
+    if (e != hipSuccess) {
+        delete g;
+        return dev_fail(e, "wall density kernel launch");
+    }
+    e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         delete g;
         return dev_fail(e, "begin capture");
     }
     lbm_status st = LBM_OK;
     if (s) {
-        const int cur0 = s->cur;
-        for (int64_t k = 0; k < nsteps && st == LBM_OK; ++k) {
-            hipError_t el = launch_one_step(s, s->cur);
-            if (el != hipSuccess) st = dev_fail(el, "step launch during capture");
-            s->cur ^= 1;
-        }
-        s->cur = cur0;  // nothing ran: restore
+        int cur = s->cur;  // nothing runs during capture: the handle keeps its state
+        int64_t done = 0;
+        hipError_t el = launch_steps(s, cur, nsteps, done);
+        if (el != hipSuccess) st = dev_fail(el, "step launch during capture");
     } else {
         st = batch_launch(b, nsteps);
     }
@@ -789,6 +860,11 @@ lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats)
             return fail(LBM_EINVAL, "the batch changed since capture (members or step parity)");
         lbm_status stc = batch_check(g->b);
         if (stc != LBM_OK) return stc;
+    }
+    if (g->s && repeats > 0) {
+        // the replayed steps read the partial sums of the state they start from
+        hipError_t e = wall_densities(g->s);
+        if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     }
     for (int64_t r = 0; r < repeats; ++r) {
         hipError_t e = hipGraphLaunch(g->exec, g->stream);

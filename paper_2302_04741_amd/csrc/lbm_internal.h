@@ -510,14 +510,26 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
 // Plates normal to y at y = -1/2 and y = ny - 1/2 (lbm_set_walls): a population
 // whose streaming source lies behind a plate is the plate's emission
 // rw[side][column of the source] * e[side][i]; populations streaming into a
-// plate stay in their slots at the node they leave (the "crossing" slots),
-// from which rw is computed before every use (wall_mass_kernel).
+// plate stay in their slots at the node they leave (the "crossing" slots).
+// A plate's density rw over column (x, z) is the sum of the
+// slots of the rows next to it whose next move crosses it, over the plate's
+// normalisation e_Q.  Those sums are kept per row ("partial sums": rows 0, 1, 2
+// for the bottom plate, ny-3+k for the top one; the same rows for both when
+// ny < 3), for each of the two population buffers: the step that writes a
+// buffer also writes its partial sums, and the next step adds the (at most 3)
+// rows of a column in order.
 struct WallDesc {
     int32_t on;
-    int32_t pad;
-    double *rw;       // [2][nx*nz] wall densities of the current state (bottom, top)
+    int32_t par;      // buffer holding the state read (0 or 1): its sums are part[par]
+    double *part;     // [2 buffer][2 plate][3 row][nx*nz] partial sums (bottom, top)
     const double *e;  // [2][Q + 1]: e_i = f0_i(1, (U_w, 0, 0), theta_w), then the normalisation
 };
+
+__host__ __device__ inline int64_t wall_part_index(int par, int side, int k, int64_t ncol,
+                                                   int64_t col)
+{
+    return ((int64_t(par) * 2 + side) * 3 + k) * ncol + col;
+}
 
 struct LaunchCfg {
     int block;  // threads along x per block
@@ -562,6 +574,10 @@ hipError_t launch_wall_mass(int lat, int storage, const void *A, const GridDims 
 hipError_t launch_wall_step(int lat, int storage, int eq, int fo, const void *A, void *B,
                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
                             const LaunchCfg &lc);
+// small grids: nsteps steps in one single-workgroup launch, A -> B -> A ...
+hipError_t launch_resident(int lat, int storage, int eq, int fo, void *A, void *B,
+                           const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                           const LaunchCfg &lc, int nsteps);
 
 // Per-lattice / per-storage pieces, each explicitly instantiated in its own
 // translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
@@ -573,6 +589,10 @@ hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl);
 template <int LAT, class S>
 hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                                const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &gd,
+                              const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc,
+                              int nsteps);
 template <int LAT>
 hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, int64_t ny,
                                double *e, hipStream_t stream);

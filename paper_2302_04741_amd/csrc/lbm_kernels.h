@@ -67,16 +67,23 @@ __device__ __forceinline__ double wall_emitted(const WallDesc &wd, const GridDim
     const int xv = wrap3(x - L::c(i, 0), gd.nx);
     const int zv = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
     const int64_t ncol = int64_t(gd.nx) * gd.nz;
-    return wd.rw[side * ncol + int64_t(zv) * gd.nx + xv] * wd.e[side * (L::Q + 1) + i] - w * rho0;
+    const int64_t col = int64_t(zv) * gd.nx + xv;
+    // the plate's density over the source column: its rows' sums, in order
+    double m = wd.part[wall_part_index(wd.par, side, 0, ncol, col)];
+    if (gd.ny > 1) m += wd.part[wall_part_index(wd.par, side, 1, ncol, col)];
+    if (gd.ny > 2) m += wd.part[wall_part_index(wd.par, side, 2, ncol, col)];
+    const double rw = m / wd.e[side * (L::Q + 1) + L::Q];
+    return rw * wd.e[side * (L::Q + 1) + i] - w * rho0;
 }
 
-template <class L, class S, class T, bool WALLS = false>
+template <class L, class S, class T, bool WALLS = false, bool LANE_ROWS = false>
 __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &gd, int x, int y,
                                        int z, T (&h)[L::Q], const WallDesc *wd = nullptr,
                                        double rho0 = 0.0)
 {
     // x offsets are per lane (7 distinct byte offsets); y and z are uniform over
-    // the block, so each row offset and each plane resource is a scalar.
+    // the wavefront, so each row offset and each plane resource is a scalar
+    // (LANE_ROWS: y and z vary per lane and the row offset joins the lane offset).
     uint32_t xs[7];
     int ys[7], zs[7];
 #pragma unroll
@@ -100,7 +107,10 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
         const uint32_t row =
             uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px) * uint32_t(sizeof(S));
         const auto r = plane_rsrc(A + int64_t(i) * P, plane_bytes);
-        h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
+        if constexpr (LANE_ROWS)
+            h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3] + row, 0u));
+        else
+            h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
     });
 }
 
@@ -127,7 +137,7 @@ template <int LAT, class S> inline int step_default_threads(int64_t waves)
 
 // The fused update of one cell (x, y, z): gather, moments, equilibrium, stress,
 // force, relaxation, store.  y and z must be uniform over the wavefront.
-template <int LAT, class S, int EQ, int FO, bool WALLS = false>
+template <int LAT, class S, int EQ, int FO, bool WALLS = false, bool LANE_ROWS = false>
 __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict__ B,
                                           const GridDims &gd, const ForceDesc &fd,
                                           const StepCoef &co, int x, int y, int z,
@@ -143,7 +153,7 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // offsets address it
 
     T h[L::Q];
-    gather<L, S, T, WALLS>(A, gd, x, y, z, h, wd, co.rho0);
+    gather<L, S, T, WALLS, LANE_ROWS>(A, gd, x, y, z, h, wd, co.rho0);
     T g[3];
     load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
 
@@ -157,22 +167,47 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // every term is a small deviation, so the rounding stays at the size of h.
     const T om = cs.om;
     const T drho = cs.drho;
-    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
-    const uint32_t ro = uint32_t(rowbase) * uint32_t(sizeof(S));
+    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S)) +
+                        (LANE_ROWS ? uint32_t(rowbase) * uint32_t(sizeof(S)) : 0u);
+    const uint32_t ro = LANE_ROWS ? 0u : uint32_t(rowbase) * uint32_t(sizeof(S));
     const uint32_t plane_bytes = uint32_t(P * int64_t(sizeof(S)));
+    // with plates: the partial sums of the state written here (the slots whose
+    // next move crosses a plate, as stored), for the next step's emission
+    double ps[2] = {0.0, 0.0};
+    auto account = [&](auto II, S stored) {
+        if constexpr (WALLS) {
+            constexpr int i = decltype(II)::value;
+            constexpr int cy = L::c(i, 1);
+            if constexpr (cy != 0) {
+                const double v = Codec<L, S>::template load<i, double>(stored) +
+                                 L::wshell(L::shell(i)) * co.rho0;
+                if constexpr (cy < 0) ps[0] += (y + cy < 0) ? v : 0.0;
+                else ps[1] += (y + cy >= gd.ny) ? v : 0.0;
+            }
+        }
+    };
     combo_pairs<L, T, EQ, FO, true>(cs, om, cs.cf, [&](auto IP, auto IM, T ev, T od) {
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip));
         const T dp = fma_t(T(w), drho, -h[ip]);
-        BufIO<S>::store(Codec<L, S>::template store<ip, T>(h[ip] + fma_t(om, dp, ev + od)),
-                        plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
+        const S sp = Codec<L, S>::template store<ip, T>(h[ip] + fma_t(om, dp, ev + od));
+        BufIO<S>::store(sp, plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
+        account(IP, sp);
         if constexpr (im >= 0) {
             const T dm = fma_t(T(w), drho, -h[im]);
-            BufIO<S>::store(Codec<L, S>::template store<im, T>(h[im] + fma_t(om, dm, ev - od)),
-                            plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
+            const S sm = Codec<L, S>::template store<im, T>(h[im] + fma_t(om, dm, ev - od));
+            BufIO<S>::store(sm, plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
+            account(IM, sm);
         }
     });
+    if constexpr (WALLS) {
+        const int64_t ncol = int64_t(gd.nx) * gd.nz;
+        const int64_t col = int64_t(z) * gd.nx + x;
+        const int y1 = gd.ny > 3 ? gd.ny - 3 : 0;  // first row of the top plate's sums
+        if (y < 3) wd->part[wall_part_index(wd->par ^ 1, 0, y, ncol, col)] = ps[0];
+        if (y >= y1) wd->part[wall_part_index(wd->par ^ 1, 1, y - y1, ncol, col)] = ps[1];
+    }
 }
 
 // Work split: one wavefront updates 64 consecutive cells of one row
@@ -204,19 +239,23 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
     step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
 }
 
-// K1c: the rows next to the plates (y < 3 and y >= ny - 3; every row when
-// ny <= 6), run after K1 has updated every row as if periodic: the same cell
-// update with the plates' emission in place of the sources behind them.
+// K1c: the step of a grid between plates, in one launch: K1's work split;
+// the wavefronts of the rows next to a plate (y < 3 or y >= ny - 3, a uniform
+// test) take the plates' emission in place of the sources behind them and
+// write the partial sums of the state they produce.
 template <int LAT, class S, int EQ, int FO>
 __global__ void __launch_bounds__(step_max_threads<S>())
     wall_step_kernel(const S *__restrict__ A, S *__restrict__ B, GridDims gd, ForceDesc fd,
                      StepCoef co, WallDesc wd)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y, z = blockIdx.z;
-    const int y = (gd.ny <= 6 || k < 3) ? k : gd.ny - 6 + k;
-    if (x >= gd.nx) return;
-    step_cell<LAT, S, EQ, FO, true>(A, B, gd, fd, co, x, y, z, &wd);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                         (threadIdx.x >> 6));
+    int x, y, z;
+    if (!wave_cell(gd, wave, x, y, z)) return;
+    if (y < 3 || y >= gd.ny - 3)
+        step_cell<LAT, S, EQ, FO, true>(A, B, gd, fd, co, x, y, z, &wd);
+    else
+        step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,31 +542,94 @@ __global__ void __launch_bounds__(64)
     }
 }
 
-template <int LAT>
-__global__ void __launch_bounds__(256)
-    wall_mass_kernel(const void *__restrict__ A, int storage, GridDims gd, StepCoef co,
-                     WallDesc wd)
+template <class L, class S>
+__device__ __forceinline__ void wall_column_density(const S *__restrict__ A, const GridDims &gd,
+                                                    const StepCoef &co, const WallDesc &wd,
+                                                    int64_t col)
 {
-    using L = Lattice<LAT>;
+    // The partial sums of state A (buffer wd.par) over one column: per row next
+    // to a plate, its slots whose next move crosses the plate -- rows y = k
+    // with c_y < -k (bottom), rows y = ny-3+k with c_y >= 3 - k (top) --
+    // populations ascending.  Every load is unconditional and independent (the
+    // crossing test only selects the term), so they are all in flight at once.
     const int64_t ncol = int64_t(gd.nx) * gd.nz;
-    const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (col >= ncol) return;
     const int x = int(col % gd.nx), z = int(col / gd.nx);
-    for (int side = 0; side < 2; ++side) {
+    static_for<0, 2>([&](auto SIDE) {
+        constexpr int side = decltype(SIDE)::value;
         const int y0 = side == 0 ? 0 : (gd.ny > 3 ? gd.ny - 3 : 0);
-        const int y1 = side == 0 ? (gd.ny < 3 ? gd.ny : 3) : gd.ny;
-        double m = 0.0;
-        for (int y = y0; y < y1; ++y) {
+        static_for<0, 3>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            const int y = y0 + k;
+            if (y >= gd.ny) return;  // uniform: only when ny < 3
             const int64_t own = (int64_t(z) * gd.ny + y) * gd.px + x;
+            double m = 0.0;
             static_for<0, L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const int yd = y + L::c(i, 1);
-                if (side == 0 ? yd < 0 : yd >= gd.ny)
-                    m += load_any<L, i>(A, storage, int64_t(i) * gd.P + own) +
-                         L::wshell(L::shell(i)) * co.rho0;
+                constexpr int cy = L::c(i, 1);
+                // a slot can cross only toward its plate
+                if constexpr (side == 0 ? cy < 0 : cy > 0) {
+                    const int yd = y + cy;
+                    const double v =
+                        Codec<L, S>::template load<i, double>(A[int64_t(i) * gd.P + own]) +
+                        L::wshell(L::shell(i)) * co.rho0;
+                    m += (side == 0 ? yd < 0 : yd >= gd.ny) ? v : 0.0;
+                }
             });
+            wd.part[wall_part_index(wd.par, side, k, ncol, col)] = m;
+        });
+    });
+}
+
+template <int LAT, class S>
+__global__ void __launch_bounds__(256)
+    wall_mass_kernel(const S *__restrict__ A, GridDims gd, StepCoef co, WallDesc wd)
+{
+    const int64_t ncol = int64_t(gd.nx) * gd.nz;
+    const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (col < ncol) wall_column_density<Lattice<LAT>, S>(A, gd, co, wd, col);
+}
+
+// ---------------------------------------------------------------------------
+// K1d: resident multi-step kernel for small grids.  One workgroup runs nsteps
+// steps in one launch, the two buffers alternating, with a workgroup barrier
+// between steps (a barrier makes the global writes before it visible to the
+// whole workgroup after it).  Each lane takes cells of the flattened grid
+// (64 consecutive cells per wavefront, across row ends), so rows vary per lane
+// and their offsets join the lane offsets.  With plates every cell takes the
+// plates' emission in place of the sources behind them (densities from the
+// partial sums the previous step wrote) and writes its row's partial sums.
+// Every cell is updated by one thread with the arithmetic of the single-grid
+// step.
+// ---------------------------------------------------------------------------
+// Largest workgroup of the resident kernel whose registers fit without
+// spilling: with plates a wavefront needs more than half the register file of
+// a SIMD (one wavefront per SIMD), without them at most half (FP64) or a
+// quarter (FP32 arithmetic).
+template <class S, bool WALLS>
+constexpr int resident_max_threads()
+{
+    return WALLS ? 256 : (sizeof(S) == 8 ? 512 : 1024);
+}
+
+template <int LAT, class S, int EQ, int FO, bool WALLS>
+__global__ void __launch_bounds__((resident_max_threads<S, WALLS>()))
+    resident_kernel(S *__restrict__ P0, S *__restrict__ P1, GridDims gd, ForceDesc fd,
+                    StepCoef co, WallDesc wd, int nsteps)
+{
+    using L = Lattice<LAT>;
+    const int64_t N = gd.N;
+    WallDesc w = wd;
+    for (int n = 0; n < nsteps; ++n) {
+        const S *A = (n & 1) ? P1 : P0;
+        S *B = (n & 1) ? P0 : P1;
+        w.par = wd.par ^ (n & 1);  // the partial sums of A; the step writes B's
+        for (int64_t c = threadIdx.x; c < N; c += blockDim.x) {
+            const int x = int(c % gd.nx);
+            const int64_t row = c / gd.nx;
+            const int y = int(row % gd.ny), z = int(row / gd.ny);
+            step_cell<LAT, S, EQ, FO, WALLS, true>(A, B, gd, fd, co, x, y, z, &w);
         }
-        wd.rw[side * ncol + col] = m / wd.e[side * (L::Q + 1) + L::Q];
+        __syncthreads();
     }
 }
 

@@ -112,13 +112,42 @@ template <int LAT, class S>
 hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                                const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
 {
-    const int bx = block_for(gd, lc.block > 0 ? std::min(lc.block, step_max_threads<S>()) : 256);
-    const dim3 grid(unsigned((gd.nx + bx - 1) / bx), unsigned(gd.ny < 6 ? gd.ny : 6),
-                    unsigned(gd.nz));
+    // the work split of the periodic step (blocks of bx/64 row wavefronts)
+    const int64_t waves = ((int64_t(gd.nx) + 63) / 64) * gd.ny * gd.nz;
+    int bx = lc.block > 0 ? lc.block : step_default_threads<LAT, S>(waves);
+    bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
+    const int64_t wpb = bx / 64;
+    const dim3 grid(unsigned((waves + wpb - 1) / wpb));
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((wall_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
                            grid, dim3(bx), 0, lc.stream, static_cast<const S *>(A),
                            static_cast<S *>(B), gd, fd, co, lc.walls);
+        return hipGetLastError();
+    });
+}
+
+template <int LAT, class S>
+hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &gd,
+                              const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc,
+                              int nsteps)
+{
+    // one workgroup: a lane per cell up to the variant's register limit
+    auto threads = [&](int cap) {
+        const int bx = lc.block > 0 ? std::min(lc.block, cap) : cap;
+        return int(std::min<int64_t>(bx, (gd.N + 63) / 64 * 64));
+    };
+    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
+        constexpr int EQ = decltype(E)::value, FO = decltype(O)::value;
+        if (lc.walls.on)
+            hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, true>), dim3(1),
+                               dim3(threads(resident_max_threads<S, true>())), 0, lc.stream,
+                               static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
+                               nsteps);
+        else
+            hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, false>), dim3(1),
+                               dim3(threads(resident_max_threads<S, false>())), 0, lc.stream,
+                               static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
+                               nsteps);
         return hipGetLastError();
     });
 }
@@ -143,8 +172,16 @@ hipError_t launch_wall_mass_l(int storage, const void *A, const GridDims &gd, co
                               const LaunchCfg &lc)
 {
     const int64_t ncol = int64_t(gd.nx) * gd.nz;
-    hipLaunchKernelGGL((wall_mass_kernel<LAT>), dim3(unsigned((ncol + 255) / 256)), dim3(256), 0,
-                       lc.stream, A, storage, gd, co, lc.walls);
+    const dim3 grid(unsigned((ncol + 255) / 256)), block(256);
+    if (storage == 0)
+        hipLaunchKernelGGL((wall_mass_kernel<LAT, double>), grid, block, 0, lc.stream,
+                           static_cast<const double *>(A), gd, co, lc.walls);
+    else if (storage == 1)
+        hipLaunchKernelGGL((wall_mass_kernel<LAT, float>), grid, block, 0, lc.stream,
+                           static_cast<const float *>(A), gd, co, lc.walls);
+    else
+        hipLaunchKernelGGL((wall_mass_kernel<LAT, __half>), grid, block, 0, lc.stream,
+                           static_cast<const __half *>(A), gd, co, lc.walls);
     return hipGetLastError();
 }
 

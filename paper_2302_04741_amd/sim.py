@@ -223,6 +223,11 @@ class Sim:
     def step_count(self, n: int):
         check(load().lbm_set_step_count(self.handle, int(n)))
 
+    def set_resident_limit(self, max_cells: int):
+        """Grids of at most max_cells cells step many steps per launch in one
+        workgroup (default 0: always one launch per step)."""
+        check(load().lbm_set_resident_limit(self.handle, int(max_cells)))
+
     def set_viscosity(self, mu: float):
         """mu > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (the
         dynamic viscosity held constant); 0: the constant tau_hat again."""

@@ -145,9 +145,9 @@ def test_workspace_size(lattice, dims, storage, sbytes, Q, D):
     pf = _lib.make_params(lattice, dims, 0.8, storage, force_field=True)
     expect_f = 2 * up(Q * P * sbytes) + up(D * N * abytes) + up(512 * Q * 8) + up(64)
     assert _lib.workspace_bytes(pf) == expect_f
-    # plates: wall densities per (x, z) column and plate, emission tables
+    # plates: partial sums per buffer, plate, row and (x, z) column; emission tables
     pw = _lib.make_params(lattice, dims, 0.8, storage, walls=True)
-    expect_w = expect + up(2 * dims[0] * dims[2] * 8) + up(2 * (Q + 1) * 8)
+    expect_w = expect + up(2 * 2 * 3 * dims[0] * dims[2] * 8) + up(2 * (Q + 1) * 8)
     assert _lib.workspace_bytes(pw) == expect_w
 
 
