@@ -140,19 +140,36 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
     return out
 
 
-def cpu_baseline(wl, steps: int):
+def _oracle_rate(wl, steps: int, nthreads: int = 0):
     import oracle
 
-    g = wl.force_field()
-    sim = oracle.OracleSim(1, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, g,
-                           force_order=wl.force_order)
+    sim = oracle.OracleSim(1, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, wl.force_field(),
+                           force_order=wl.force_order, nthreads=nthreads)
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": wl.ncell * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+    return wl.ncell * steps / dt / 1e6, dt
+
+
+def cpu_baseline(wl, steps: int):
+    import oracle
+
+    from paper_2302_04741_amd import workloads
+
+    v, dt = _oracle_rate(wl, steps)
+    cores = oracle.num_threads()
+    # one host thread, on a 64^3 grid of the same workload (a bounded sample);
+    # the thread count is process-wide, so it is restored afterwards
+    small = workloads.kolmogorov_3d(n=64, tau_hat=wl.tau_hat)
+    v1, dt1 = _oracle_rate(small, 2, nthreads=1)
+    oracle.num_threads(cores)
+    return {"value": v, "unit": "MLUPS",
+            "cores": cores, "kind": "oracle",
             "sample": "FP64 oracle, full %dx%dx%d grid of the same workload, %d steps "
-                      "(%.1f s, init excluded), %s" % (*wl.dims, steps, dt, _cpu_model())}
+                      "(%.1f s, init excluded), %s" % (*wl.dims, steps, dt, _cpu_model()),
+            "single_thread": {"value": round(v1, 3), "unit": "MLUPS",
+                              "sample": "FP64 oracle, one thread, 64^3 grid of the same "
+                                        "workload, 2 steps (%.1f s)" % dt1}}
 
 
 def _cpu_model() -> str:
@@ -300,6 +317,44 @@ def bench_serve(args) -> dict:
     }
 
 
+def bench_channel(args) -> dict:
+    """The channel of Sec. 3 (D2Q37 3 x 150 between plates, per-cell tau): time
+    per step of the plated step kernel, one launch per step, timed with HIP
+    events on the handle's stream over --steps steps after --warmup."""
+    import torch
+
+    from paper_2302_04741_amd import sim as lbm_sim
+    from paper_2302_04741_amd import workloads
+
+    wl = workloads.channel()
+    stream = torch.cuda.Stream()
+    s = lbm_sim.from_workload(wl, storage=args.storage, stream=stream)
+    s.step(args.warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream.synchronize()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.steps
+    s.totals()  # raises on a non-finite state
+    s.close()
+    return {
+        "metric": "channel step time",
+        "value": round(us, 3),
+        "unit": "us/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": False,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": wl.name + ", per-cell tau, %s storage" % args.storage.upper()},
+        "mlups": round(wl.ncell / us, 3),
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,9 +372,10 @@ def main(argv=None) -> int:
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary under profiles/ and exit (no GPU)")
-    ap.add_argument("--workload", default="step", choices=["step", "batch", "serve"],
+    ap.add_argument("--workload", default="step", choices=["step", "batch", "serve", "channel"],
                     help="step: the fused step on one grid (default); batch: a mix of "
-                         "independent grids, batched vs sequential; serve: the request stream")
+                         "independent grids, batched vs sequential; serve: the request stream; "
+                         "channel: the plated 3 x 150 channel, time per step")
     ap.add_argument("--mix", default="serve", choices=["serve", "small"],
                     help="batch: grid sizes of the serving stream or small grids")
     ap.add_argument("--count", type=int, default=0,
@@ -351,6 +407,8 @@ def main(argv=None) -> int:
         if args.workload == "batch":
             args.count = args.count or 64
             out = bench_batch(args)
+        elif args.workload == "channel":
+            out = bench_channel(args)
         else:
             args.count = args.count or 256
             out = bench_serve(args)

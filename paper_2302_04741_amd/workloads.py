@@ -32,6 +32,8 @@ from typing import Tuple
 import numpy as np
 
 LATTICE_DIM = {"D2Q37": 2, "D3Q39": 3}
+# lattice spacing r of each velocity set (velocities are r times integer vectors)
+LATTICE_R = {"D2Q37": 1.1969797703930745, "D3Q39": math.sqrt(1.5)}
 
 #: seed of the random phases of the 3-D velocity perturbation
 KOLMOGOROV_SEED = 230204741
@@ -114,6 +116,26 @@ def thermal_shear_2d(n: int = 1024, tau_hat: float = 0.6, dtheta: float = 0.02,
     name = "D2Q37 %dx%d shear, tau=%g dtheta=%g Ma=%g" % (n, ny, tau_hat, dtheta, mach)
     return Workload(name, "D2Q37", dims, tau_hat, rho, u, theta,
                     ("uniform", np.asarray(g, np.float64)), steps, force_order=force_order)
+
+
+def channel(theta_b: float = 0.7, theta_t: float = 1.4, nx: int = 3, ny: int = 150,
+            u_c: float = 1.5, re: float = 1800.0, steps: int = 150_000,
+            force_order: int = 4) -> Workload:
+    """The channel of Sec. 3: D2Q37 between plates at rest (height H = ny r),
+    dynamic viscosity mu = rho0 U_c H / Re held constant by the per-cell
+    relaxation time, g_x = 8 mu U_c / (rho0 H^2) along the channel and
+    g_y = -50 g_x across it (rho0 = 1).  Starts from rest at uniform density
+    with theta linear between the plate temperatures."""
+    H = ny * LATTICE_R["D2Q37"]
+    mu = u_c * H / re
+    gx = 8.0 * mu * u_c / H ** 2
+    dims = (nx, ny, 1)
+    _, y, _ = _grid(dims)
+    theta = theta_b + (theta_t - theta_b) * (y + 0.5) / ny
+    name = "D2Q37 %dx%d channel, plates %g/%g" % (nx, ny, theta_b, theta_t)
+    return Workload(name, "D2Q37", dims, 0.8, np.ones(nx * ny), np.zeros((2, nx * ny)), theta,
+                    ("uniform", np.array([gx, -50.0 * gx])), steps, force_order=force_order,
+                    mu=mu, walls=(theta_b, theta_t, 0.0, 0.0))
 
 
 def kolmogorov_modes():

@@ -53,3 +53,24 @@ def test_shear_workload_fields():
     np.testing.assert_allclose(wl.theta, 1 + 0.1 * s)
     np.testing.assert_allclose(wl.u[0], 0.2 * np.sqrt(1 + 0.1 * s) * s)
     assert np.all(wl.u[1] == 0) and np.all(wl.rho == 1)
+
+
+def test_lattice_spacing_matches_library():
+    from paper_2302_04741_amd import _lib
+
+    for lat in ("D2Q37", "D3Q39"):
+        _, _, r = _lib.lattice_table(lat)
+        assert abs(workloads.LATTICE_R[lat] - r) < 1e-15 * r
+
+
+def test_channel_workload():
+    """The channel of Sec. 3: U_c = rho0 g_x H^2 / (8 mu) with mu = U_c H / Re."""
+    wl = workloads.channel()
+    H = 150 * workloads.LATTICE_R["D2Q37"]
+    assert wl.dims == (3, 150, 1) and wl.walls == (0.7, 1.4, 0.0, 0.0)
+    gx, gy = wl.force[1]
+    assert abs(gx * H ** 2 / (8 * wl.mu) - 1.5) < 1e-12
+    assert abs(wl.mu - 1.5 * H / 1800.0) < 1e-15
+    assert gy == -50 * gx
+    th = wl.theta.reshape(150, 3)
+    assert np.all(th[:, 0] == th[:, 2]) and 0.7 < th.min() < th.max() < 1.4
