@@ -39,15 +39,15 @@
  *                                (diffuse reflection, mass balanced per column),
  *                                described at or_walls below.
  *
- * Readings where the paper is silent or garbled (all documented in the design
- * notes of the repository):
+ * Readings where the paper is silent or garbled:
  *   - stored variable f~ = f + (f - f0)/(2 tau) - F/2 (the auxiliary variable of
  *     the trapezoidal time integration); hence u-bar = u~ + g/2 and
  *     theta-bar = (E/rho - |u~|^2 + |g|^2/4)/D with E = sum f~ |xi|^2;
  *   - sigma-bar = -(1 - 1/(2 tau^)) sum_i (f~_i - f0bar_i)(xi_i - u-bar)(xi_i - u-bar),
  *     then its trace (zero in exact arithmetic) is removed;
  *   - initial state f~ = f0(rho0,u0,theta0) - F(rho0,u0,theta0,g,sigma=0)/2;
- *   - every grid is periodic in every axis.
+ *   - every grid is periodic in every axis, except across the plates when they
+ *     are on (then periodic in x and z only).
  */
 #include <math.h>
 #include <stdint.h>
