@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "lbm.h"
 #include "lbm_internal.h"
 
@@ -47,6 +49,15 @@ struct lbm_sim {
 namespace {
 
 thread_local std::string g_err;
+
+// A roctx range over one API call (shown by rocprofv3 --marker-trace around
+// the kernels the call enqueues; a few nanoseconds when no profiler listens).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 lbm_status fail(lbm_status st, const char *fmt, ...)
 {
@@ -370,6 +381,7 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps)
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return ok();
+    TraceRange range("lbm_step");
     hipError_t e = wall_densities(s);
     if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     int cur = s->cur;
@@ -756,6 +768,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     if (b->sims.empty()) return fail(LBM_EINVAL, "batch has no members (call lbm_batch_set)");
     lbm_status st = batch_check(b);
     if (st != LBM_OK) return st;
+    TraceRange range("lbm_batch_step");
     st = batch_launch(b, nsteps);
     if (st != LBM_OK) return st;
     batch_advance(b, nsteps);
@@ -861,6 +874,7 @@ lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats)
         lbm_status stc = batch_check(g->b);
         if (stc != LBM_OK) return stc;
     }
+    TraceRange range("lbm_graph_launch");
     if (g->s && repeats > 0) {
         // the replayed steps read the partial sums of the state they start from
         hipError_t e = wall_densities(g->s);

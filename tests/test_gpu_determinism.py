@@ -52,9 +52,17 @@ def test_resume_from_checkpoint_is_bitwise(sim_mod):
     assert torch.equal(c.get_populations(), ref)
 
 
-def test_nan_canary_every_output_written(sim_mod):
+@pytest.mark.parametrize("plates,resident", [(False, False), (True, False), (False, True),
+                                             (True, True)])
+def test_nan_canary_every_output_written(sim_mod, plates, resident):
+    """Every slot of the output buffer is written by a step (the single-grid
+    kernel, the kernel with plates, the resident kernel)."""
     wl = workloads.random_smooth("D2Q37", (67, 7, 1), seed=5, force_kind="uniform")
+    if plates:
+        wl.walls = (0.9, 1.1, 0.0, 0.0)
     s = sim_mod.from_workload(wl)
+    if resident:
+        s.set_resident_limit(1 << 40)
     s.step(1)
     # fill the state with NaN, then restore a valid state and step: every
     # element of the output buffer must be overwritten by finite values
