@@ -37,6 +37,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+# the arithmetic type of each storage form (F16 deviations are computed in FP32)
+ARITH = {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_d3q39_f32_256cube_pmc.txt")
 
 
@@ -259,7 +261,7 @@ def bench_batch(args) -> dict:
         "steps": args.steps,
         "warmup": args.warmup,
         "higher_is_better": True,
-        "dtype": args.storage,
+        "dtype": ARITH[args.storage],
         "data": "synthetic",
         "config": {"workload": "%d D2Q37 grids (%s mix, seed %d), %d cells in all, %s storage"
                                % (len(wls), args.mix, args.seed, cells, args.storage.upper()),
@@ -297,7 +299,7 @@ def bench_serve(args) -> dict:
         "unit": "s (p99 latency)",
         "n_gpus": 1,
         "higher_is_better": False,
-        "dtype": args.storage,
+        "dtype": ARITH[args.storage],
         "data": "synthetic",
         "config": {"workload": "%d D2Q37 requests, Poisson %.0f/s (seed %d), L ~ U{64..1024}, "
                                "%d steps each, %s storage, %d slots, %.1f GiB budget, "
@@ -348,7 +350,7 @@ def bench_channel(args) -> dict:
         "steps": args.steps,
         "warmup": args.warmup,
         "higher_is_better": False,
-        "dtype": args.storage,
+        "dtype": ARITH[args.storage],
         "data": "synthetic",
         "config": {"workload": wl.name + ", per-cell tau, %s storage" % args.storage.upper()},
         "mlups": round(wl.ncell / us, 3),
@@ -482,7 +484,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}[args.storage],
+        "dtype": ARITH[args.storage],
         "data": "synthetic",
         "config": {
             "workload": "D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=%g, "
