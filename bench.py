@@ -27,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,15 +43,21 @@ ARITH = {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_d3q39_f32_256cube_pmc.txt")
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources that make up the step kernel."""
+    """Hash of the HIP sources that make up the library, comments and blank
+    lines left out (an edit of a comment does not change what was measured)."""
     csrc = os.path.join(ROOT, "paper_2302_04741_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                code = _COMMENT.sub("", fh.read())
+            lines = [ln.rstrip() for ln in code.splitlines() if ln.strip()]
+            h.update(name.encode())
+            h.update("\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

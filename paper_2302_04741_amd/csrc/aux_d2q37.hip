@@ -1,4 +1,4 @@
-// Initialisation, moments, heat-flux and totals kernels for D2Q37.
+// Initialisation, moments, heat-flux, totals and plate kernels for D2Q37.
 #include "lbm_launch.h"
 
 namespace lbm {

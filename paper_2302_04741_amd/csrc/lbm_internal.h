@@ -566,7 +566,8 @@ struct BatchLaunch {
     hipStream_t stream;
 };
 hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl);
-// plates: emission tables, wall densities, and the step of the rows next to them
+// plates: emission tables, the row sums of a state no step produced, and the
+// step of a grid between plates
 hipError_t launch_wall_setup(int lat, int eq, const double *theta, const double *uw, int64_t ny,
                              double *e, hipStream_t stream);
 hipError_t launch_wall_mass(int lat, int storage, const void *A, const GridDims &gd,

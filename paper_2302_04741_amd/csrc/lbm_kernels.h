@@ -495,10 +495,12 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // K6: plates.  wall_setup_kernel: e_i = f0_i(1, (U_w, 0, 0), theta_w) of both
 // plates in FP64 and the normalisation sum_{i entering} min(|c_iy|, ny) e_i.
-// wall_mass_kernel: per (x, z) column and plate, the mass of the crossing
-// slots (populations about to stream into the plate, rows y < 3 or
-// y >= ny - 3, summed y ascending then i ascending) over that normalisation:
-// the density rw at which the plate re-emits exactly what it absorbs.
+// wall_mass_kernel: per (x, z) column, plate and row next to the plate, the
+// mass of the crossing slots (populations about to stream into the plate),
+// for a state no step produced (after initialisation or an external write);
+// a step writes the same sums for the state it produces.  The plate's density
+// rw over a column, at which it re-emits exactly what it absorbs, is the sum
+// of its rows' sums over the normalisation.
 // ---------------------------------------------------------------------------
 template <int LAT, int EQ>
 __global__ void __launch_bounds__(64)

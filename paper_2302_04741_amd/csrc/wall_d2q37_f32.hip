@@ -1,4 +1,4 @@
-// Step of the rows next to the plates for D2Q37 storage f32 (all equilibrium and force orders).
+// Step of a grid between plates (one launch per step) for D2Q37 storage f32 (all equilibrium and force orders).
 #include "lbm_launch.h"
 
 namespace lbm {
