@@ -271,8 +271,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->Q = lattice_q(p->lattice);
     s->eq = p->eq_order ? p->eq_order : lattice_maxeq(p->lattice);
     s->N = p->nx * p->ny * p->nz;
-    s->gd = GridDims{int32_t(p->nx), int32_t(p->ny), int32_t(p->nz), int32_t(row_pitch(p->nx)),
-                     s->N, row_pitch(p->nx) * p->ny * p->nz};
+    s->gd = make_grid_dims(p->nx, p->ny, p->nz, row_pitch(p->nx));
     s->co = StepCoef{1.0 / p->tau_hat, 1.0 - 0.5 / p->tau_hat, p->rho0, 0.0};
     s->fd = ForceDesc{};
     s->stream = static_cast<hipStream_t>(hip_stream);

@@ -20,6 +20,7 @@
 
 #include <type_traits>
 
+#include "fastdiv.h"
 #include "lattice_tables.h"
 
 namespace lbm {
@@ -161,10 +162,19 @@ constexpr int ROW_ALIGN = 64;
 
 struct GridDims {
     int32_t nx, ny, nz;
-    int32_t px;  // row pitch of the population planes
-    int64_t N;   // cells, nx*ny*nz
-    int64_t P;   // values per population plane, px*ny*nz
+    int32_t px;     // row pitch of the population planes
+    int64_t N;      // cells, nx*ny*nz
+    int64_t P;      // values per population plane, px*ny*nz
+    DivU32 by_wpr;  // division by the wavefronts per row, ceil(nx / 64)
+    DivU32 by_ny;   // division by ny
 };
+
+inline GridDims make_grid_dims(int64_t nx, int64_t ny, int64_t nz, int64_t px)
+{
+    return GridDims{int32_t(nx), int32_t(ny), int32_t(nz), int32_t(px), nx * ny * nz,
+                    px * ny * nz, make_divu32(uint32_t((nx + 63) / 64)),
+                    make_divu32(uint32_t(ny))};
+}
 
 struct ForceDesc {
     int32_t kind;  // 0 uniform, 1 axis profile, 2 field

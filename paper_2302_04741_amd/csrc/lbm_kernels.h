@@ -218,11 +218,12 @@ __device__ __forceinline__ bool wave_cell(const GridDims &gd, uint32_t wave, int
                                           int &z)
 {
     const uint32_t k = (uint32_t(gd.nx) + 63u) >> 6;  // wavefronts per row
-    const uint32_t row = wave / k;
+    const uint32_t row = divu(gd.by_wpr, wave);
     if (row >= uint32_t(gd.ny) * uint32_t(gd.nz)) return false;
     x = int((wave - row * k) * 64u + (threadIdx.x & 63u));
-    y = int(row % uint32_t(gd.ny));
-    z = int(row / uint32_t(gd.ny));
+    const uint32_t zz = divu(gd.by_ny, row);
+    y = int(row - zz * uint32_t(gd.ny));
+    z = int(zz);
     return x < gd.nx;
 }
 
@@ -289,9 +290,10 @@ __global__ void __launch_bounds__(256)
         // tiles of one simulation number fewer than its cells (< 2^32)
         const uint32_t k = uint32_t(t - begin[lo]);
         const uint32_t cx = uint32_t(sd.chunks_x);
-        const uint32_t row = k / cx;
+        const uint32_t row = divu(sd.gd.by_wpr, k);  // chunks_x = ceil(nx / 64)
         const uint32_t xc = k - row * cx;
-        const int y = int(row % uint32_t(sd.gd.ny)), z = int(row / uint32_t(sd.gd.ny));
+        const uint32_t zz = divu(sd.gd.by_ny, row);
+        const int y = int(row - zz * uint32_t(sd.gd.ny)), z = int(zz);
         const int x = int(xc * 64u + (threadIdx.x & 63u));
         const int c = sd.cur ^ parity;
         const S *A = static_cast<const S *>(sd.pop[c]);
