@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import LATTICES, check, load
+from ._lib import check, load
 
 DIM = {"D2Q37": 2, "D3Q39": 3}
 

@@ -7,10 +7,9 @@
 * a request whose initial state is not finite fails alone, the others finish;
 * p50/p99 latency and aggregate MLUPS are reported.
 """
-import numpy as np
 import pytest
 
-from paper_2302_04741_amd import serve, workloads
+from paper_2302_04741_amd import serve
 
 pytestmark = pytest.mark.gpu
 

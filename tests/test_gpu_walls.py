@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from _parity import LAT_ID, gpu_moments, oracle_run, rel_err, to_host
+from _parity import gpu_moments, oracle_run, rel_err, to_host
 from paper_2302_04741_amd import workloads
 
 pytestmark = pytest.mark.gpu

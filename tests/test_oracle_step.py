@@ -26,7 +26,6 @@
   uniform state reduces to the constant-tau run with tau-hat = mu/(rho theta)
   + 1/2; q_err holds with tau = mu/(rho theta).
 """
-import math
 
 import numpy as np
 import pytest

@@ -15,7 +15,6 @@ mass re-emitted per column.  Pinned by what any consistent wall must satisfy:
   the channel height doubles (first order in the Knudsen number).
 """
 import numpy as np
-import pytest
 
 from oracle import fd_poiseuille as fd
 

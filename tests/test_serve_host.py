@@ -1,6 +1,5 @@
 """Host-side logic of the serving loop (CPU only): the request generator and the
 slot / HBM-budget admission accounting."""
-import math
 
 import numpy as np
 import pytest
