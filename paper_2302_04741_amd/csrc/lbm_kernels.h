@@ -620,7 +620,6 @@ __global__ void __launch_bounds__((resident_max_threads<S, WALLS>()))
     resident_kernel(S *__restrict__ P0, S *__restrict__ P1, GridDims gd, ForceDesc fd,
                     StepCoef co, WallDesc wd, int nsteps)
 {
-    using L = Lattice<LAT>;
     const int64_t N = gd.N;
     WallDesc w = wd;
     for (int n = 0; n < nsteps; ++n) {
