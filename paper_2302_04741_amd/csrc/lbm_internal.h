@@ -135,6 +135,12 @@ template <class L> constexpr int c2(int i)
 // stores h_i * 2^k_i as binary16, with k_i = round(-log2 w_i): the exact
 // power-of-two scale brings deviations of the size of w_i to about one, far
 // from the subnormal range of binary16.
+// The factor a stored value carries relative to the deviation it stands for:
+// 1 for FP64 and FP32 storage (reduced-precision storage supplies its own).
+struct UnitScale {
+    template <int I> static constexpr double scale() { return 1.0; }
+};
+
 template <class L> struct DevScale {
     static constexpr int k(int i)
     {
@@ -261,11 +267,17 @@ template <class T> struct RawSums {
     T drho, j[3], P[3][3];
 };
 
-template <class L, class T>
+//
+// SC::scale<i>() is the factor the values carry (1, or the power of two of
+// reduced-precision storage, the same for every velocity of a shell): the
+// sums take it out through their constants, so scaled and unscaled inputs
+// give bitwise the same sums.
+template <class L, class T, class SC = UnitScale>
 __device__ __forceinline__ RawSums<T> raw_sums(const T (&h)[L::Q])
 {
     RawSums<T> s;
-    s.drho = h[0];
+    constexpr double u0 = 1.0 / SC::template scale<0>();
+    s.drho = (u0 == 1.0) ? h[0] : h[0] * T(u0);
     for (int a = 0; a < 3; ++a) {
         s.j[a] = T(0);
         for (int b = 0; b < 3; ++b) s.P[a][b] = T(0);
@@ -273,21 +285,26 @@ __device__ __forceinline__ RawSums<T> raw_sums(const T (&h)[L::Q])
     static_for<0, (L::Q - 1) / 2>([&](auto K) {
         constexpr int ip = 1 + 2 * decltype(K)::value;
         constexpr int im = ip + 1;
+        static_assert(SC::template scale<ip>() == SC::template scale<im>(),
+                      "a pair shares its scale");
+        constexpr double u = 1.0 / SC::template scale<ip>();  // exact: a power of two
         const T sp = h[ip] + h[im];
         const T dm = h[ip] - h[im];
-        s.drho += sp;
+        // acc += m * v with the scale folded into m: one rounding, as unscaled
+        auto add = [&](T &acc, int m, T v) {
+            if (u == 1.0 && m == 1) acc += v;
+            else if (u == 1.0 && m == -1) acc -= v;
+            else acc = fma_t(v, T(m * u), acc);
+        };
+        add(s.drho, 1, sp);
         static_for<0, L::D>([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int ca = L::c(ip, a);
-            if constexpr (ca == 1) s.j[a] += dm;
-            else if constexpr (ca == -1) s.j[a] -= dm;
-            else if constexpr (ca != 0) s.j[a] += T(ca) * dm;
+            if constexpr (ca != 0) add(s.j[a], ca, dm);
             static_for<a, L::D>([&](auto B) {
                 constexpr int b = decltype(B)::value;
                 constexpr int cab = ca * L::c(ip, b);
-                if constexpr (cab == 1) s.P[a][b] += sp;
-                else if constexpr (cab == -1) s.P[a][b] -= sp;
-                else if constexpr (cab != 0) s.P[a][b] += T(cab) * sp;
+                if constexpr (cab != 0) add(s.P[a][b], cab, sp);
             });
         });
     });
@@ -369,12 +386,15 @@ __device__ __forceinline__ void finish_moments(const RawSums<T> &s, const T g[3]
 //               w rho [xg (1 + (xu^2 - u2 + t(X2 - D - 2))/2) - gu xu]   (order >= 3)
 //               - (w/2) [xg (xi.sigma.xi) - 2 xi.sigma.g]     (order 4)
 // With NO_BASE the even part omits alpha * w * rho (the leading term of f0),
-// so that callers can add it as an exactly rounded increment.
+// so that callers can add it as an exactly rounded increment.  With a scale
+// SC every w is w * SC::scale<i>() (a power of two): even and odd come out
+// multiplied by it exactly.
 // The callback receives (i_plus, i_minus, even, odd) for each pair and
 // (0, -1, even, 0) for the rest velocity; the indices are passed as
 // std::integral_constant so that callers index register arrays statically.
 // ---------------------------------------------------------------------------
-template <class L, class T, int EQ, int FO, bool NO_BASE = false, class CB>
+template <class L, class T, int EQ, int FO, bool NO_BASE = false, class SC = UnitScale,
+          class CB>
 __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T beta, CB &&cb)
 {
     constexpr int D = L::D;
@@ -416,7 +436,11 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
         }();
         constexpr double X2d = L::R2 * c2<L>(iref);
         const T X2 = T(X2d);
-        const T wr = T(L::wshell(s)) * rho;
+        // the shell's weight times the scale its values carry (a power of two):
+        // every constant below is linear in it, so even and odd come out
+        // scaled, rounding for rounding
+        constexpr double ws = L::wshell(s) * SC::template scale<iref>();
+        const T wr = T(ws) * rho;
         const T A = alpha * wr;      // multiplies the equilibrium bracket
         const T Bf = beta * wr;      // multiplies the force bracket
         // e0 - 1, computed without the leading 1
@@ -449,7 +473,7 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
             Kb2 = T(0);
         }
         Kbf = Bf;                       // even, times xg xu
-        Kw = beta * T(0.5 * L::wshell(s));  // (beta w / 2) for the sigma terms
+        Kw = beta * T(0.5 * ws);            // (beta w / 2) for the sigma terms
     };
 
     // rest velocity

@@ -29,9 +29,18 @@ template <> struct ArithOf<double> { using type = double; };
 template <> struct ArithOf<float> { using type = float; };
 template <> struct ArithOf<__half> { using type = float; };
 
+// load/store convert between a stored value and the deviation h_i it stands
+// for; load_scaled/store_scaled keep the factor scale<I>() the stored value
+// carries (the fused step works on scaled values: see raw_sums, combo_pairs).
 template <class L, class S> struct Codec {
+    template <int I> static constexpr double scale() { return 1.0; }
     template <int I, class T> __device__ static __forceinline__ T load(S v) { return T(v); }
     template <int I, class T> __device__ static __forceinline__ S store(T h) { return S(h); }
+    template <int I, class T> __device__ static __forceinline__ T load_scaled(S v) { return T(v); }
+    template <int I, class T> __device__ static __forceinline__ S store_scaled(T h)
+    {
+        return S(h);
+    }
 };
 
 // F16 deviations: stored value h_i 2^k_i, k_i = round(-log2 w_i).
@@ -51,6 +60,14 @@ template <class L> struct Codec<L, __half> {
     {
         constexpr double sc = scale<I>();
         return __float2half_rn(float(h * T(sc)));
+    }
+    template <int I, class T> __device__ static __forceinline__ T load_scaled(__half v)
+    {
+        return T(__half2float(v));
+    }
+    template <int I, class T> __device__ static __forceinline__ __half store_scaled(T h)
+    {
+        return __float2half_rn(float(h));
     }
 };
 
@@ -100,7 +117,9 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
         if constexpr (WALLS) {
             const int ysrc = y - cy;  // uniform over the block
             if (ysrc < 0 || ysrc >= gd.ny) {
-                h[i] = T(wall_emitted<L>(*wd, gd, i, L::wshell(L::shell(i)), rho0, x, y, z));
+                constexpr double sc = Codec<L, S>::template scale<i>();  // a power of two
+                h[i] = T(sc * wall_emitted<L>(*wd, gd, i, L::wshell(L::shell(i)), rho0, x, y,
+                                              z));
                 return;
             }
         }
@@ -108,9 +127,10 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
             uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px) * uint32_t(sizeof(S));
         const auto r = plane_rsrc(A + int64_t(i) * P, plane_bytes);
         if constexpr (LANE_ROWS)
-            h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3] + row, 0u));
+            h[i] = Codec<L, S>::template load_scaled<i, T>(
+                BufIO<S>::load(r, xs[cx + 3] + row, 0u));
         else
-            h[i] = Codec<L, S>::template load<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
+            h[i] = Codec<L, S>::template load_scaled<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
     });
 }
 
@@ -152,12 +172,16 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // one population plane is < 4 GiB (checked at creation), so 32-bit byte
     // offsets address it
 
+    // h holds the deviations as stored, times Codec::scale<i>() (1 unless the
+    // storage is reduced-precision); the sums and the pair terms take the
+    // scale through their constants, so no value is rescaled on the way.
+    using C = Codec<L, S>;
     T h[L::Q];
     gather<L, S, T, WALLS, LANE_ROWS>(A, gd, x, y, z, h, wd, co.rho0);
     T g[3];
     load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
 
-    const RawSums<T> rs = raw_sums<L, T>(h);
+    const RawSums<T> rs = raw_sums<L, T, C>(h);
     CellState<T> cs;
     finish_moments<L, T, FO == 4>(rs, g, co, cs);
 
@@ -186,17 +210,17 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
             }
         }
     };
-    combo_pairs<L, T, EQ, FO, true>(cs, om, cs.cf, [&](auto IP, auto IM, T ev, T od) {
+    combo_pairs<L, T, EQ, FO, true, C>(cs, om, cs.cf, [&](auto IP, auto IM, T ev, T od) {
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
-        constexpr double w = L::wshell(L::shell(ip));
+        constexpr double w = L::wshell(L::shell(ip)) * C::template scale<ip>();
         const T dp = fma_t(T(w), drho, -h[ip]);
-        const S sp = Codec<L, S>::template store<ip, T>(h[ip] + fma_t(om, dp, ev + od));
+        const S sp = C::template store_scaled<ip, T>(h[ip] + fma_t(om, dp, ev + od));
         BufIO<S>::store(sp, plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
         account(IP, sp);
         if constexpr (im >= 0) {
             const T dm = fma_t(T(w), drho, -h[im]);
-            const S sm = Codec<L, S>::template store<im, T>(h[im] + fma_t(om, dm, ev - od));
+            const S sm = C::template store_scaled<im, T>(h[im] + fma_t(om, dm, ev - od));
             BufIO<S>::store(sm, plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
             account(IM, sm);
         }
