@@ -38,6 +38,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+# block sizes at which the bare access pattern is timed
+PATTERN_BLOCKS = (256, 512, 1024)
 # the arithmetic type of each storage form (F16 deviations are computed in FP32)
 ARITH = {"f32": "f32", "f64": "f64", "f16dev": "f16 storage, f32 arithmetic"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_d3q39_f32_256cube_pmc.txt")
@@ -457,6 +459,26 @@ def main(argv=None) -> int:
         e1.record(stream)
         torch.cuda.synchronize()
         rep_ms.append(e0.elapsed_time(e1) / args.steps)
+    # the ceiling of the step's access pattern: the same traffic without the
+    # arithmetic (lbm_pattern_pass), at each block size, the best one kept (at
+    # the step's own shape the bare pattern can be slower than the step: with
+    # no arithmetic between them, more loads and stores are in flight at once)
+    pat_ms = {}
+    if args.repeats > 0:
+        for blk in PATTERN_BLOCKS:
+            s.set_block(blk)
+            best = None
+            for _ in range(2):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                s.pattern_pass(args.steps)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                best = ms if best is None else min(best, ms)
+            pat_ms[blk] = best
+        s.set_block(args.block)
     rho, u, th = s.moments()
     finite = bool(torch.isfinite(u).all().item() and torch.isfinite(th).all().item())
     if not finite:
@@ -512,6 +534,17 @@ def main(argv=None) -> int:
         },
         "wall_s_timed_region": round(wall, 4),
     }
+    if pat_ms:
+        by_block = {str(b): round(bytes_per_launch / (ms * 1e-3) / 1e9, 1)
+                    for b, ms in pat_ms.items()}
+        pat = max(by_block.values())
+        out["pattern_ceiling"] = {
+            "achieved": pat, "unit": "GB/s",
+            "what": "the step's loads and stores alone, no arithmetic (lbm_pattern_pass), "
+                    "best over block sizes, %d passes each" % args.steps,
+            "by_block": by_block,
+            "step_frac": round(achieved / pat, 4),
+        }
     if rep_ms:
         med = sorted(rep_ms)[len(rep_ms) // 2]
         out["repeats"] = {"count": len(rep_ms), "steps_each": args.steps,

@@ -171,6 +171,16 @@ LBM_API lbm_status lbm_totals(lbm_sim *s, double *out);
  * step (the quantity q_err of Sec. 2 refers to).  q: D*N device doubles. */
 LBM_API lbm_status lbm_heat_flux(lbm_sim *s, double *q);
 
+/* Access-pattern diagnostic: `repeats` passes of the memory traffic of the
+ * step alone -- the streaming of eq. (lbm): every population read from its
+ * pull source x - c_i and written back unchanged at the cell's own slot of
+ * the idle population buffer, with the step's work split and launch shape but
+ * none of its arithmetic.  The state, the step count and everything a later
+ * call reads are unchanged (a step overwrites the idle buffer whole).  Timing
+ * it beside lbm_step gives the ceiling of the step's access pattern on the
+ * device.  Async on the handle's stream; LBM_EINVAL if repeats < 0. */
+LBM_API lbm_status lbm_pattern_pass(lbm_sim *s, int64_t repeats);
+
 /* Raw population state for checkpoint/restart: lbm_population_bytes bytes,
  * dense SoA planes of h_i in the storage type, value i*N + cell (the padding
  * of the internal rows is dropped), post-collision "pull" layout.  get copies

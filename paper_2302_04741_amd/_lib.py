@@ -29,7 +29,8 @@ FLAG_WALLS = 2
 #: the C-ABI entry points, in the order include/lbm.h declares them
 API_SYMBOLS = (
     "lbm_workspace_bytes", "lbm_create", "lbm_set_force", "lbm_step", "lbm_moments",
-    "lbm_destroy", "lbm_last_error", "lbm_totals", "lbm_heat_flux", "lbm_population_bytes",
+    "lbm_destroy", "lbm_last_error", "lbm_totals", "lbm_heat_flux", "lbm_pattern_pass",
+    "lbm_population_bytes",
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
     "lbm_set_stream", "lbm_set_block", "lbm_set_resident_limit", "lbm_set_viscosity",
     "lbm_set_walls", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set",
@@ -97,6 +98,8 @@ def load() -> ctypes.CDLL:
     L.lbm_totals.restype = _i32
     L.lbm_heat_flux.argtypes = [_vp, _vp]
     L.lbm_heat_flux.restype = _i32
+    L.lbm_pattern_pass.argtypes = [_vp, _i64]
+    L.lbm_pattern_pass.restype = _i32
     L.lbm_population_bytes.argtypes = [_vp]
     L.lbm_population_bytes.restype = _sz
     L.lbm_get_populations.argtypes = [_vp, _vp]

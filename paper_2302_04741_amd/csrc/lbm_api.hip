@@ -440,6 +440,18 @@ lbm_status lbm_heat_flux(lbm_sim *s, double *q)
     return ok();
 }
 
+lbm_status lbm_pattern_pass(lbm_sim *s, int64_t repeats)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (repeats < 0) return fail(LBM_EINVAL, "repeats must be >= 0");
+    for (int64_t r = 0; r < repeats; ++r) {
+        hipError_t e = launch_pattern(s->p.lattice, s->p.storage, s->pop[s->cur],
+                                      s->pop[s->cur ^ 1], s->gd, cfg(s));
+        if (e != hipSuccess) return dev_fail(e, "pattern kernel launch");
+    }
+    return ok();
+}
+
 size_t lbm_population_bytes(const lbm_sim *s)
 {
     if (!s) return 0;

@@ -26,6 +26,18 @@ hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_pattern(int lat, int storage, const void *A, void *B, const GridDims &gd,
+                          const LaunchCfg &lc)
+{
+    if (lat == 0 && storage == 0) return launch_pattern_ls<0, double>(A, B, gd, lc);
+    if (lat == 0 && storage == 1) return launch_pattern_ls<0, float>(A, B, gd, lc);
+    if (lat == 1 && storage == 0) return launch_pattern_ls<1, double>(A, B, gd, lc);
+    if (lat == 1 && storage == 1) return launch_pattern_ls<1, float>(A, B, gd, lc);
+    if (lat == 0 && storage == 2) return launch_pattern_ls<0, __half>(A, B, gd, lc);
+    if (lat == 1 && storage == 2) return launch_pattern_ls<1, __half>(A, B, gd, lc);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_wall_setup(int lat, int eq, const double *theta, const double *uw, int64_t ny,
                              double *e, hipStream_t stream)
 {

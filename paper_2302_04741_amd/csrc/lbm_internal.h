@@ -572,6 +572,8 @@ struct LaunchCfg {
 };
 
 // Generic entry points (lbm_dispatch.hip), switching on lattice and storage.
+hipError_t launch_pattern(int lat, int storage, const void *A, void *B, const GridDims &gd,
+                          const LaunchCfg &lc);
 hipError_t launch_step(int lat, int storage, int eq, int fo, const void *A, void *B,
                        const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
                        const LaunchCfg &lc);
@@ -624,6 +626,8 @@ hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl);
 template <int LAT, class S>
 hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const GridDims &gd,
                                const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_pattern_ls(const void *A, void *B, const GridDims &gd, const LaunchCfg &lc);
 template <int LAT, class S>
 hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &gd,
                               const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc,

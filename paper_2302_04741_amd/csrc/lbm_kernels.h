@@ -264,6 +264,30 @@ __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__
     step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
 }
 
+// K7 (diagnostic): the memory traffic of K1 alone -- every population read
+// from its pull source and written unchanged at the cell's own slot of the
+// other buffer, K1's work split, no arithmetic.  Its rate is the ceiling of
+// K1's access pattern on the device.
+template <int LAT, class S>
+__global__ void __launch_bounds__(step_max_threads<S>())
+    pattern_kernel(const S *__restrict__ A, S *__restrict__ B, GridDims gd)
+{
+    using L = Lattice<LAT>;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
+                                                         (threadIdx.x >> 6));
+    int x, y, z;
+    if (!wave_cell(gd, wave, x, y, z)) return;
+    S h[L::Q];
+    gather<L, S, S>(A, gd, x, y, z, h);
+    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
+    const uint32_t ro = uint32_t((int64_t(z) * gd.ny + y) * gd.px) * uint32_t(sizeof(S));
+    const uint32_t plane_bytes = uint32_t(gd.P * int64_t(sizeof(S)));
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        BufIO<S>::store(h[i], plane_rsrc(B + int64_t(i) * gd.P, plane_bytes), xo, ro);
+    });
+}
+
 // K1c: the step of a grid between plates, in one launch: K1's work split;
 // the wavefronts of the rows next to a plate (y < 3 or y >= ny - 3, a uniform
 // test) take the plates' emission in place of the sources behind them and

@@ -52,6 +52,20 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
 }
 
 template <int LAT, class S>
+hipError_t launch_pattern_ls(const void *A, void *B, const GridDims &gd, const LaunchCfg &lc)
+{
+    // the launch shape of the step (blocks of bx/64 row wavefronts)
+    const int64_t waves = ((int64_t(gd.nx) + 63) / 64) * gd.ny * gd.nz;
+    int bx = lc.block > 0 ? lc.block : step_default_threads<LAT, S>(waves);
+    bx = bx < step_max_threads<S>() ? bx : step_max_threads<S>();
+    const int64_t wpb = bx / 64;
+    hipLaunchKernelGGL((pattern_kernel<LAT, S>), dim3(unsigned((waves + wpb - 1) / wpb)),
+                       dim3(bx), 0, lc.stream, static_cast<const S *>(A), static_cast<S *>(B),
+                       gd);
+    return hipGetLastError();
+}
+
+template <int LAT, class S>
 hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl)
 {
     if (bl.ntiles <= 0) return hipSuccess;

@@ -1,8 +1,11 @@
-// Fused step kernels for D3Q39 with F16 deviation storage (FP32 arithmetic).
+// Fused step kernels for D3Q39 with F16 deviation storage (FP32 arithmetic), and the
+// access-pattern diagnostic.
 #include "lbm_launch.h"
 
 namespace lbm {
 template hipError_t launch_step_ls<1, __half>(int, int, const void *, void *, const GridDims &,
                                                 const ForceDesc &, const StepCoef &,
                                                 const LaunchCfg &);
+template hipError_t launch_pattern_ls<1, __half>(const void *, void *, const GridDims &,
+                                                  const LaunchCfg &);
 }  // namespace lbm

@@ -223,6 +223,12 @@ class Sim:
     def step_count(self, n: int):
         check(load().lbm_set_step_count(self.handle, int(n)))
 
+    def pattern_pass(self, repeats: int = 1):
+        """Diagnostic: `repeats` passes of the step's memory traffic without its
+        arithmetic (the state is unchanged); its rate is the ceiling of the
+        step's access pattern."""
+        check(load().lbm_pattern_pass(self.handle, int(repeats)))
+
     def set_resident_limit(self, max_cells: int):
         """Grids of at most max_cells cells step many steps per launch in one
         workgroup (default 0: always one launch per step)."""

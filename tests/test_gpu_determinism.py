@@ -113,3 +113,23 @@ def test_force_errors_on_gpu(sim_mod):
         s.set_force([float("nan"), 0.0])
     with pytest.raises(LbmError):
         s.set_block(96)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_pattern_pass_leaves_the_state(sim_mod, storage):
+    """The access-pattern diagnostic writes only the idle buffer: the state and
+    every later step are bitwise those of a run without it."""
+    wl = workloads.random_smooth("D3Q39", (70, 9, 6), seed=11, force_kind="axis")
+    a = sim_mod.from_workload(wl, storage=storage)
+    b = sim_mod.from_workload(wl, storage=storage)
+    a.step(3)
+    b.step(3)
+    before = a.get_populations().clone()
+    a.pattern_pass(2)
+    assert torch.equal(a.get_populations(), before)
+    assert a.step_count == 3
+    a.step(4)
+    b.step(4)
+    assert torch.equal(a.get_populations(), b.get_populations())
+    with pytest.raises(Exception):
+        a.pattern_pass(-1)

@@ -158,6 +158,7 @@ def test_null_handle_calls(lib):
     assert lib.lbm_set_force(None, 0, None, 0, 0) == _lib.LBM_EINVAL
     assert lib.lbm_totals(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_heat_flux(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_pattern_pass(None, 1) == _lib.LBM_EINVAL
     assert lib.lbm_get_populations(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_set_populations(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_set_step_count(None, 0) == _lib.LBM_EINVAL
