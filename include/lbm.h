@@ -236,9 +236,8 @@ LBM_API lbm_status lbm_set_viscosity(lbm_sim *s, double mu);
  * emission balancing the initial outgoing populations).  A step with plates is
  * still one launch: the step that writes a state also writes, per row next to
  * a plate, the sums the next step's emission needs.  enable = 0 removes the
- * plates.  Handles with plates cannot join a batch (LBM_EUNSUPPORTED from
- * lbm_batch_set).  LBM_EINVAL on bad values, a missing flag or a stepped
- * handle. */
+ * plates.  Handles with plates may join a batch (their plates included).
+ * LBM_EINVAL on bad values, a missing flag or a stepped handle. */
 LBM_API lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double theta_t,
                                  double u_b, double u_t);
 
@@ -259,9 +258,9 @@ LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
  * balances uneven members; with a block count set, a persistent grid walks the
  * list with a fixed stride.
  * Members must share lattice, storage, eq_order and force_order; grid sizes,
- * tau_hat, mu, rho0 and forces may differ.  The per-cell arithmetic is that of
- * lbm_step, so a member's result does not depend on the other members or on
- * the launch shape.  Runs on hip_stream. */
+ * tau_hat, mu, rho0, forces and plates may differ.  The per-cell arithmetic is
+ * that of lbm_step, so a member's result does not depend on the other members
+ * or on the launch shape.  Runs on hip_stream. */
 LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
                                     void *hip_stream, lbm_batch **out);
 

@@ -185,14 +185,16 @@ constexpr int64_t RESIDENT_MAX_STEPS_PER_LAUNCH = 4096;
 // state: steps keep them (each writes those of the state it produces); after
 // the state was written otherwise (initialisation, lbm_set_populations) one
 // pass over the columns computes them.
-hipError_t wall_densities(lbm_sim *s)
+hipError_t wall_densities(lbm_sim *s, hipStream_t stream)
 {
     if (!s->wd.on || s->wall_fresh) return hipSuccess;
-    hipError_t e =
-        launch_wall_mass(s->p.lattice, s->p.storage, s->pop[s->cur], s->gd, s->co, cfg(s));
+    LaunchCfg c = cfg(s);
+    c.stream = stream;
+    hipError_t e = launch_wall_mass(s->p.lattice, s->p.storage, s->pop[s->cur], s->gd, s->co, c);
     s->wall_fresh = e == hipSuccess;
     return e;
 }
+hipError_t wall_densities(lbm_sim *s) { return wall_densities(s, s->stream); }
 
 bool resident(const lbm_sim *s) { return s->N <= s->resident_max; }
 
@@ -609,6 +611,7 @@ struct lbm_batch {
     int threads;     // threads per block (tiles of 64 cells, one per wavefront)
     int64_t blocks;  // 0: one block per tile
     bool upload_pending;  // an asynchronous upload may still read `host`
+    bool walls;           // some member has plates
 };
 
 struct lbm_graph {
@@ -641,13 +644,24 @@ lbm_status batch_check(const lbm_batch *b)
     return LBM_OK;
 }
 
+// Members between plates need the row sums of their current state; those the
+// state was not produced by a step get them on the batch's stream.
+hipError_t batch_wall_densities(lbm_batch *b)
+{
+    for (lbm_sim *s : b->sims) {
+        hipError_t e = wall_densities(s, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 lbm_status batch_launch(lbm_batch *b, int64_t nsteps)
 {
     const lbm_sim *s0 = b->sims[0];
     for (int64_t k = 0; k < nsteps; ++k) {
         const int parity = int((b->steps_done + k) & 1);
-        const BatchLaunch bl{b->begin,  b->table,   int(b->sims.size()), b->ntiles,
-                             parity,    b->threads, b->blocks,           b->stream};
+        const BatchLaunch bl{b->begin,  b->table,   int(b->sims.size()), b->ntiles, parity,
+                             b->threads, b->blocks, b->stream,           b->walls};
         hipError_t e = launch_multi_step(s0->p.lattice, s0->p.storage, s0->eq, s0->p.force_order,
                                          bl);
         if (e != hipSuccess) return dev_fail(e, "multi-grid step launch");
@@ -675,7 +689,6 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
             s->p.force_order != s0->p.force_order)
             return fail(LBM_EINVAL,
                         "batch members must share lattice, storage, eq_order and force_order");
-        if (s->wd.on) return fail(LBM_EUNSUPPORTED, "sims[%d] has plates; batches are periodic", k);
         TileSim &t = tab[k];
         t.pop[0] = s->pop[0];
         t.pop[1] = s->pop[1];
@@ -685,6 +698,7 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
         t.gd = s->gd;
         t.fd = s->fd;
         t.co = s->co;
+        t.wd = s->wd;
         begin[k] = tiles;
         tiles += int64_t(t.chunks_x) * s->p.ny * s->p.nz;
     }
@@ -710,6 +724,8 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
     b->steps_done = 0;
     b->generation++;
     b->ntiles = tiles;
+    b->walls = false;
+    for (lbm_sim *s : b->sims) b->walls = b->walls || s->wd.on;
     return LBM_OK;
 }
 
@@ -757,6 +773,7 @@ lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_
     b->threads = BATCH_DEFAULT_THREADS;
     b->blocks = 0;
     b->upload_pending = false;
+    b->walls = false;
     *out = b;
     return ok();
 }
@@ -780,8 +797,13 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     lbm_status st = batch_check(b);
     if (st != LBM_OK) return st;
     TraceRange range("lbm_batch_step");
+    hipError_t e = batch_wall_densities(b);
+    if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     st = batch_launch(b, nsteps);
-    if (st != LBM_OK) return st;
+    if (st != LBM_OK) {
+        for (lbm_sim *s : b->sims) s->wall_fresh = false;
+        return st;
+    }
     batch_advance(b, nsteps);
     return ok();
 }
@@ -835,7 +857,7 @@ lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph 
     g->gen = s ? s->gen : b->generation;
     g->cur0 = s ? s->cur : 0;
     g->parity0 = b ? int32_t(b->steps_done & 1) : 0;
-    hipError_t e = s ? wall_densities(s) : hipSuccess;  // not part of the capture
+    hipError_t e = s ? wall_densities(s) : batch_wall_densities(b);  // not captured
     if (e != hipSuccess) {
         delete g;
         return dev_fail(e, "wall density kernel launch");
@@ -886,9 +908,9 @@ lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats)
         if (stc != LBM_OK) return stc;
     }
     TraceRange range("lbm_graph_launch");
-    if (g->s && repeats > 0) {
+    if (repeats > 0) {
         // the replayed steps read the partial sums of the state they start from
-        hipError_t e = wall_densities(g->s);
+        hipError_t e = g->s ? wall_densities(g->s) : batch_wall_densities(g->b);
         if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     }
     for (int64_t r = 0; r < repeats; ++r) {

@@ -197,6 +197,30 @@ struct StepCoef {
     double mu;   // > 0: per-cell tau^ = mu/(rho theta) + 1/2 replaces om and cf
 };
 
+// Plates normal to y at y = -1/2 and y = ny - 1/2 (lbm_set_walls): a population
+// whose streaming source lies behind a plate is the plate's emission
+// rw[side][column of the source] * e[side][i]; populations streaming into a
+// plate stay in their slots at the node they leave (the "crossing" slots).
+// A plate's density rw over column (x, z) is the sum of the
+// slots of the rows next to it whose next move crosses it, over the plate's
+// normalisation e_Q.  Those sums are kept per row ("partial sums": rows 0, 1, 2
+// for the bottom plate, ny-3+k for the top one; the same rows for both when
+// ny < 3), for each of the two population buffers: the step that writes a
+// buffer also writes its partial sums, and the next step adds the (at most 3)
+// rows of a column in order.
+struct WallDesc {
+    int32_t on;
+    int32_t par;      // buffer holding the state read (0 or 1): its sums are part[par]
+    double *part;     // [2 buffer][2 plate][3 row][nx*nz] partial sums (bottom, top)
+    const double *e;  // [2][Q + 1]: e_i = f0_i(1, (U_w, 0, 0), theta_w), then the normalisation
+};
+
+__host__ __device__ inline int64_t wall_part_index(int par, int side, int k, int64_t ncol,
+                                                   int64_t col)
+{
+    return ((int64_t(par) * 2 + side) * 3 + k) * ncol + col;
+}
+
 // One member of a multi-grid batch (device table entry).  Its tiles are runs
 // of 64 cells along x (one wavefront each): chunks_x per grid row, rows in
 // (z, y) order.
@@ -208,6 +232,7 @@ struct TileSim {
     GridDims gd;
     ForceDesc fd;
     StepCoef co;
+    WallDesc wd;         // plates (off for a periodic member); wd.par is set per step
 };
 
 // Periodic wrap of v in [-3, n + 3) into [0, n), valid for any n >= 1.
@@ -541,29 +566,6 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// Plates normal to y at y = -1/2 and y = ny - 1/2 (lbm_set_walls): a population
-// whose streaming source lies behind a plate is the plate's emission
-// rw[side][column of the source] * e[side][i]; populations streaming into a
-// plate stay in their slots at the node they leave (the "crossing" slots).
-// A plate's density rw over column (x, z) is the sum of the
-// slots of the rows next to it whose next move crosses it, over the plate's
-// normalisation e_Q.  Those sums are kept per row ("partial sums": rows 0, 1, 2
-// for the bottom plate, ny-3+k for the top one; the same rows for both when
-// ny < 3), for each of the two population buffers: the step that writes a
-// buffer also writes its partial sums, and the next step adds the (at most 3)
-// rows of a column in order.
-struct WallDesc {
-    int32_t on;
-    int32_t par;      // buffer holding the state read (0 or 1): its sums are part[par]
-    double *part;     // [2 buffer][2 plate][3 row][nx*nz] partial sums (bottom, top)
-    const double *e;  // [2][Q + 1]: e_i = f0_i(1, (U_w, 0, 0), theta_w), then the normalisation
-};
-
-__host__ __device__ inline int64_t wall_part_index(int par, int side, int k, int64_t ncol,
-                                                   int64_t col)
-{
-    return ((int64_t(par) * 2 + side) * 3 + k) * ncol + col;
-}
 
 struct LaunchCfg {
     int block;  // threads along x per block
@@ -600,6 +602,7 @@ struct BatchLaunch {
     int threads;            // threads per block (64, 128 or 256): 1, 2 or 4 tiles
     int64_t blocks;         // 0: one block per tile; > 0: persistent walk
     hipStream_t stream;
+    bool walls;             // some member has plates (the kernel variant that handles them)
 };
 hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl);
 // plates: emission tables, the row sums of a state no step produced, and the

@@ -317,9 +317,11 @@ __global__ void __launch_bounds__(step_max_threads<S>())
 // the grid is persistent and every wavefront exits after at most
 // ceil(ntiles / W) tiles.  Each cell is updated by exactly one thread with the
 // arithmetic of the single-grid step, so no result depends on the launch shape
-// or on the other members.
+// or on the other members.  The WALLS variant (launched when some member has
+// plates) updates the rows next to a member's plates as K1c does; periodic
+// batches keep the variant without that code.
 // ---------------------------------------------------------------------------
-template <int LAT, class S, int EQ, int FO>
+template <int LAT, class S, int EQ, int FO, bool WALLS>
 __global__ void __launch_bounds__(256)
     multi_step_kernel(const int64_t *__restrict__ begin, const TileSim *__restrict__ sims,
                       int nsims, int64_t ntiles, int parity)
@@ -346,7 +348,17 @@ __global__ void __launch_bounds__(256)
         const int c = sd.cur ^ parity;
         const S *A = static_cast<const S *>(sd.pop[c]);
         S *B = static_cast<S *>(const_cast<void *>(sd.pop[c ^ 1]));
-        if (x < sd.gd.nx) step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
+        if (x >= sd.gd.nx) continue;
+        if constexpr (WALLS) {
+            // a member between plates: its rows next to a plate as in K1c
+            if (sd.wd.on && (y < 3 || y >= sd.gd.ny - 3)) {
+                WallDesc w = sd.wd;
+                w.par = c;
+                step_cell<LAT, S, EQ, FO, true>(A, B, sd.gd, sd.fd, sd.co, x, y, z, &w);
+                continue;
+            }
+        }
+        step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
     }
 }
 

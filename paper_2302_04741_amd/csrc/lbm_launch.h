@@ -76,9 +76,15 @@ hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl)
     int64_t grid = bl.blocks > 0 ? std::min(bl.blocks, need) : need;
     grid = std::min<int64_t>(grid, 0x7fffffff);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
-        hipLaunchKernelGGL((multi_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
-                           dim3(unsigned(grid)), dim3(unsigned(bl.threads)), 0, bl.stream,
-                           bl.begin, bl.table, bl.nsims, bl.ntiles, bl.parity);
+        constexpr int EQ = decltype(E)::value, FO = decltype(O)::value;
+        if (bl.walls)
+            hipLaunchKernelGGL((multi_step_kernel<LAT, S, EQ, FO, true>), dim3(unsigned(grid)),
+                               dim3(unsigned(bl.threads)), 0, bl.stream, bl.begin, bl.table,
+                               bl.nsims, bl.ntiles, bl.parity);
+        else
+            hipLaunchKernelGGL((multi_step_kernel<LAT, S, EQ, FO, false>), dim3(unsigned(grid)),
+                               dim3(unsigned(bl.threads)), 0, bl.stream, bl.begin, bl.table,
+                               bl.nsims, bl.ntiles, bl.parity);
         return hipGetLastError();
     });
 }
