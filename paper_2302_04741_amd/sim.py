@@ -306,7 +306,7 @@ class Graph:
 class Batch:
     """Several Sims advanced together by the multi-grid kernel: one launch per
     step for all members (same lattice, storage and orders; any grid sizes,
-    relaxation times and forces)."""
+    relaxation times, forces and plates)."""
 
     def __init__(self, max_sims: int, device=None, stream=None):
         torch = _torch()
