@@ -199,8 +199,7 @@ LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
  * 1024; FP64 storage uses at most 256), i.e. wavefronts per block, each
  * wavefront updating 64 consecutive cells of one row.  0 restores the default
  * (256; 128 for FP64 storage; 1024 for D3Q39 FP32 grids of at least 2^17
- * wavefronts; on grids of at most 4096 wavefronts 1024 for D2Q37 FP32, 512 for
- * D3Q39 FP32 and 256 for FP64).  Results do not depend on it. */
+ * wavefronts).  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
 /* Small grids: a handle with at most max_cells cells steps in a single-workgroup

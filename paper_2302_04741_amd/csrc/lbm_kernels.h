@@ -148,14 +148,10 @@ template <class S> constexpr int step_max_threads()
 // storage on grids of at least 2^17 wavefronts (256^3: +2%, 384^3: +2%; on
 // smaller D3Q39 grids and on every D2Q37 grid 16-wavefront blocks lose 5-20%,
 // F16 storage loses 5% with them) and 2 for FP64 storage (D3Q39 256^3: +6%,
-// D2Q37 1024^2: +4% over 4; FP64 cannot use more than 4).  Grids of at most
-// 4096 wavefronts (one fill of the chip) take larger blocks: D2Q37 FP32 16
-// (512^2: +7%), D3Q39 FP32 8 (64^3: +4%), FP64 4 (512^2: +6%).
+// D2Q37 1024^2: +4% over 4; FP64 cannot use more than 4).
 template <int LAT, class S> inline int step_default_threads(int64_t waves)
 {
-    const bool small = waves <= 4096;
-    if (sizeof(S) == 8) return small ? 256 : 128;
-    if (sizeof(S) == 4 && small) return LAT == 0 ? 1024 : 512;
+    if (sizeof(S) == 8) return 128;
     return (LAT == 1 && sizeof(S) == 4 && waves >= (int64_t(1) << 17)) ? 1024 : 256;
 }
 
