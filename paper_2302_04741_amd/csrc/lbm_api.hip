@@ -38,7 +38,8 @@ struct lbm_sim {
     double *totals_dev;
     int64_t step;
     int block;
-    int64_t gen;  // bumped when launch arguments change (force, block, stream, plates)
+    int64_t gen;  // bumped when launch arguments change (force, block, stream, viscosity,
+                  // plates, resident limit): batches and graphs built before are stale
     WallDesc wd;  // plates (off unless lbm_set_walls)
     int64_t resident_max;  // grids of at most this many cells step in one workgroup
     double *wall_part;     // plates: partial sums of the crossing slots, per buffer
