@@ -67,3 +67,8 @@ def test_committed_summary_is_read_back():
     raises."""
     v = bench.measured_traffic()
     assert v is None or v > 0
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().err
