@@ -253,3 +253,34 @@ def test_viscosity_mode_can_be_switched_off(sim_mod, oracle_mod):
         s.set_viscosity(-1.0)
     with pytest.raises(LbmError):
         s.set_viscosity(float("nan"))
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q37", (20, 17, 1)), ("D3Q39", (9, 7, 6))])
+def test_no_force_makes_the_force_orders_coincide(sim_mod, oracle_mod, lat, dims):
+    """Degenerate case g = 0: every force term vanishes, so the four force
+    orders run the same scheme (to rounding) and each meets the oracle.  (The u
+    metric is relative to max|u|, so the gas is given a uniform drift, which no
+    viscosity damps: on a gas that comes to rest it would magnify rounding noise
+    of the density.)"""
+    outs = []
+    for fo in (1, 2, 3, 4):
+        wl = workloads.random_smooth(lat, dims, seed=4, force_kind="uniform", g_amp=0.0,
+                                     force_order=fo)
+        drift = np.array([0.03, -0.02, 0.01])[:wl.D]
+        wl.u = np.ascontiguousarray(wl.u + drift[:, None])
+        check_parity(sim_mod, oracle_mod, wl, 40)
+        outs.append(run_gpu(sim_mod, wl, 40))
+    for o in outs[1:]:
+        errs = rel_err(o, outs[0])
+        assert max(errs) < 1e-14, errs
+
+
+@pytest.mark.parametrize("tau", [0.5005, 1.0, 40.0])
+def test_relaxation_time_extremes(sim_mod, oracle_mod, tau):
+    """tau^ near 1/2 (almost inviscid), exactly 1 (the collision replaces f~ by
+    the equilibrium plus force), and large (almost no relaxation): parity holds
+    at every one of them on smooth low-amplitude fields."""
+    wl = workloads.random_smooth("D2Q37", (24, 20, 1), seed=6, tau_hat=tau, amp_u=0.01,
+                                 amp_rho=0.005, amp_theta=0.01, force_kind="uniform",
+                                 g_amp=1e-4)
+    check_parity(sim_mod, oracle_mod, wl, 60)
