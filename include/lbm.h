@@ -103,9 +103,11 @@ typedef struct {
 } lbm_params;
 
 /* Bytes of device workspace a handle needs for these parameters (256-byte
- * aligned sub-buffers included): two population arrays of Q planes whose rows
- * are padded to a multiple of 64 values, the force table, and the reduction
- * scratch of lbm_totals.  Returns 0 if the parameters are invalid. */
+ * aligned sub-buffers included): two arrays of the Q populations f~_i of
+ * eq. (lbm), in planes whose rows are padded to a multiple of 64 values, the
+ * force table, and the reduction scratch of lbm_totals (with LBM_FLAG_WALLS
+ * also the plates' row sums and emission tables).  Returns 0 if the
+ * parameters are invalid. */
 LBM_API size_t lbm_workspace_bytes(const lbm_params *p);
 
 /* Create a handle and initialise the populations from FP64 device fields.
@@ -118,9 +120,10 @@ LBM_API size_t lbm_workspace_bytes(const lbm_params *p);
  *               cell]); cell = (z*ny + y)*nx + x.  Read by an init kernel queued
  *               on hip_stream: the caller may reuse them once that stream
  *               has passed this call.
- * The initial stored state is f~ = f0(rho, u, theta) - F/2 with the current
- * force (zero until lbm_set_force), so lbm_moments reports exactly the inputs
- * at step 0.  Returns LBM_EINVAL / LBM_EUNSUPPORTED / LBM_ENOSPACE without
+ * The initial stored state is f~ = f0(rho, u, theta) - F/2 (the auxiliary
+ * variable of eq. (lbm) at n = 0, with f0 of eq. (fN) and F of eq. (fi) at
+ * sigma = 0) with the current force (zero until lbm_set_force), so
+ * lbm_moments reports exactly the inputs at step 0.  Returns LBM_EINVAL / LBM_EUNSUPPORTED / LBM_ENOSPACE without
  * queuing work, LBM_EDEVICE if the launch fails. */
 LBM_API lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_bytes,
                       void *hip_stream, const double *rho, const double *u,
@@ -149,18 +152,19 @@ LBM_API lbm_status lbm_step(lbm_sim *s, int64_t nsteps);
  * outputs: rho[N], u[D*N] (component-major), theta[N]; any may be NULL. */
 LBM_API lbm_status lbm_moments(lbm_sim *s, double *rho, double *u, double *theta);
 
-/* Destroy the handle (NULL is a no-op).  Does not free the workspace and does
- * not wait for queued work; the workspace may be reused once the stream has
- * drained. */
+/* Destroy the handle (NULL is a no-op; housekeeping, no passage of the paper).
+ * Does not free the workspace and does not wait for queued work; the
+ * workspace may be reused once the stream has drained. */
 LBM_API void lbm_destroy(lbm_sim *s);
 
-/* Thread-local message of the last failed call ("" if none). */
+/* Thread-local message of the last failed call ("" if none; housekeeping). */
 LBM_API const char *lbm_last_error(void);
 
 /* ---- diagnostics, checkpointing and tables (not part of the step path) ---- */
 
-/* Global sums over the grid of the stored populations, reduced in FP64 in a
- * fixed order (bitwise reproducible):
+/* Global sums over the grid of the stored populations (the moments of
+ * eq. (rut1) summed over all cells: mass, momentum and twice the energy of f~),
+ * reduced in FP64 in a fixed order (bitwise reproducible):
  * out[0] = sum f~, out[1..D] = sum f~ xi_a, out[D+1] = sum f~ |xi|^2 (host,
  * D+2 doubles).  Synchronises the handle's stream.  Returns LBM_ENONFINITE if
  * any sum is not finite. */
@@ -181,8 +185,9 @@ LBM_API lbm_status lbm_heat_flux(lbm_sim *s, double *q);
  * device.  Async on the handle's stream; LBM_EINVAL if repeats < 0. */
 LBM_API lbm_status lbm_pattern_pass(lbm_sim *s, int64_t repeats);
 
-/* Raw population state for checkpoint/restart: lbm_population_bytes bytes,
- * dense SoA planes of h_i in the storage type, value i*N + cell (the padding
+/* Raw population state for checkpoint/restart (the stored f~_i of eq. (lbm),
+ * as deviations): lbm_population_bytes bytes, dense SoA planes of h_i in the
+ * storage type, value i*N + cell (the padding
  * of the internal rows is dropped), post-collision "pull" layout.  get copies
  * out, set copies in (device buffers, async on the handle's stream).
  * Restoring a state together with lbm_set_step_count resumes bitwise. */
@@ -192,18 +197,20 @@ LBM_API lbm_status lbm_set_populations(lbm_sim *s, const void *src);
 LBM_API int64_t lbm_step_count(const lbm_sim *s);
 LBM_API lbm_status lbm_set_step_count(lbm_sim *s, int64_t n);
 
-/* Change the stream of a handle (work already queued stays where it is). */
+/* Change the stream of a handle (work already queued stays where it is;
+ * housekeeping, no passage of the paper). */
 LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
 
-/* Kernel launch shape of the step: threads per block (64, 128, 256, 512 or
+/* Kernel launch shape of the step of eq. (lbm) (an implementation choice, not
+ * the paper's): threads per block (64, 128, 256, 512 or
  * 1024; FP64 storage uses at most 256), i.e. wavefronts per block, each
  * wavefront updating 64 consecutive cells of one row.  0 restores the default
  * (256; 128 for FP64 storage; 1024 for D3Q39 FP32 grids of at least 2^17
  * wavefronts).  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
-/* Small grids: a handle with at most max_cells cells steps in a single-workgroup
- * kernel that runs many steps per launch (a workgroup barrier between steps)
+/* Small grids: a handle with at most max_cells cells steps (eq. (lbm), the same
+ * arithmetic) in a single-workgroup kernel that runs many steps per launch (a workgroup barrier between steps)
  * instead of one launch per step.  Off by default (0): one
  * compute unit doing every cell costs about as much per step as a launch over
  * the whole chip, so it pays only on the smallest grids (a few hundred cells).
@@ -246,12 +253,15 @@ LBM_API lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, dou
 typedef struct lbm_batch lbm_batch; /* opaque host handle */
 typedef struct lbm_graph lbm_graph; /* opaque host handle */
 
-/* Device workspace of a batch of up to max_sims simulations (its tile table:
+/* Device workspace of a batch of up to max_sims simulations (execution only,
+ * no passage of the paper; its tile table:
  * 8 * (max_sims + 1) bytes of tile offsets, rounded up to 256, then one
  * descriptor per member). */
 LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
 
-/* A batch advances its member simulations together: every step is ONE launch
+/* A batch advances its member simulations together, each by eq. (lbm) exactly
+ * as lbm_step does (an execution choice; the paper treats one grid): every step
+ * is ONE launch
  * of a multi-grid kernel over a list of tiles spanning all members (one tile =
  * 64 consecutive cells of one grid row of one member, updated by one
  * wavefront).  By default every tile gets its own wavefront and the hardware
@@ -270,25 +280,26 @@ LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t wo
  * Destroying a member leaves the batch unusable until the next lbm_batch_set. */
 LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count);
 
-/* Advance every member by nsteps (>= 0) steps, one launch per step, on the
- * batch's stream.  The library does not order that stream with the members'
+/* Advance every member by nsteps (>= 0) steps of eq. (lbm), one launch per
+ * step, on the batch's stream.  The library does not order that stream with the members'
  * own streams: work queued on a member's stream must be complete (or ordered
  * with events) before, and later work on it must wait for the batch's stream
  * (the Python binding does both). */
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
-/* Launch shape of the multi-grid kernel.  threads: threads per block, 64, 128
+/* Launch shape of the multi-grid kernel (an implementation choice).  threads: threads per block, 64, 128
  * or 256 (0 = 128), i.e. 1, 2 or 4 tiles per block; blocks: 0 = enough blocks
  * for one wavefront per tile (default), > 0 = a persistent grid of that many
  * blocks (at most 2^31 - 1).  Results do not depend on the shape.  Graphs
  * captured before must be captured again. */
 LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks);
 
-/* NULL-safe; does not free the workspace.  Waits only for the last tile-table
+/* Housekeeping; NULL-safe; does not free the workspace.  Waits only for the last tile-table
  * upload (it reads host memory owned by the batch), not for queued steps. */
 LBM_API void lbm_batch_destroy(lbm_batch *b);
 
-/* Capture nsteps (even, > 0) steps of one simulation (s) or one batch (b) --
+/* Capture nsteps (even, > 0) steps of eq. (lbm) of one simulation (s) or one
+ * batch (b) --
  * exactly one of them non-NULL -- into a HIP graph on its stream, which must
  * not be the null stream.  Capturing executes nothing and leaves the state
  * unchanged.  The graph holds the buffers of the handle: it stays valid while
@@ -296,18 +307,20 @@ LBM_API void lbm_batch_destroy(lbm_batch *b);
  * step rebuilds in place, so it is fine; a new lbm_batch_set is not). */
 LBM_API lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph **out);
 
-/* Replay the captured steps `repeats` times (asynchronous on the stream). */
+/* Replay the captured steps of eq. (lbm) `repeats` times (asynchronous on the
+ * stream). */
 LBM_API lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats);
 
-/* NULL-safe. */
+/* Housekeeping; NULL-safe. */
 LBM_API void lbm_graph_destroy(lbm_graph *g);
 
-/* The velocity set compiled into the library (host call, no GPU needed):
- * c: Q*3 ints, w: Q doubles, r: the scale with xi_i = r c_i.  Returns Q, or a
+/* The velocity set compiled into the library (host call, no GPU needed): the
+ * Gauss-Hermite rule of Sec. 2 (D2Q37 of Sec. 3, r ~ 1.19698; D3Q39 built the
+ * same way).  c: Q*3 ints, w: Q doubles, r: the scale with xi_i = r c_i.  Returns Q, or a
  * negative lbm_status. */
 LBM_API int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r);
 
-/* Library version string. */
+/* Library version string (housekeeping). */
 LBM_API const char *lbm_version(void);
 
 #ifdef __cplusplus
