@@ -294,8 +294,9 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
  * captured before must be captured again. */
 LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks);
 
-/* Housekeeping; NULL-safe; does not free the workspace.  Waits only for the last tile-table
- * upload (it reads host memory owned by the batch), not for queued steps. */
+/* Housekeeping; NULL-safe; does not free the workspace.  Waits only for the
+ * last tile-table upload (it reads host memory owned by the batch), not for
+ * queued steps. */
 LBM_API void lbm_batch_destroy(lbm_batch *b);
 
 /* Capture nsteps (even, > 0) steps of eq. (lbm) of one simulation (s) or one
