@@ -35,3 +35,47 @@ def test_bench_line_fields():
     p = d["pattern_ceiling"]
     assert p["achieved"] > 0 and set(p["by_block"]) == {"256", "512", "1024"}
     assert d["repeats"]["count"] == 2
+
+
+@pytest.mark.parametrize("storage,floor", [("f32", 0.90), ("f16dev", 0.85)])
+def test_step_stays_near_its_pattern_ceiling(storage, floor):
+    """Performance guard, relative to the same box: the fused step on the
+    256^3 benchmark grid moves its bytes at least `floor` times as fast as its
+    own loads and stores do without the arithmetic (best block size), so a
+    change that slows the kernel fails here whatever the box's absolute speed.
+    Measured: FP32 1.02-1.03, F16 0.94-0.98."""
+    import torch
+
+    from paper_2302_04741_amd import sim, workloads
+
+    wl = workloads.kolmogorov_3d(n=256)
+    s = sim.from_workload(wl, storage=storage, stream=torch.cuda.current_stream())
+    st = torch.cuda.current_stream()
+
+    def per_call(f, n=30):
+        f(3)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            f(n)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / n
+            best = ms if best is None else min(best, ms)
+        return best
+
+    step = per_call(s.step)
+    pattern = None
+    for blk in (256, 512, 1024):
+        s.set_block(blk)
+        t = per_call(s.pattern_pass)
+        pattern = t if pattern is None else min(pattern, t)
+    s.set_block(0)
+    s.close()
+    ratio = pattern / step  # bytes per step are the same for both
+    print("%s: step %.4f ms, best bare pattern %.4f ms, ratio %.3f" % (storage, step, pattern,
+                                                                        ratio), flush=True)
+    assert ratio >= floor
