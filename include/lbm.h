@@ -144,7 +144,9 @@ LBM_API lbm_status lbm_create(const lbm_params *p, void *workspace, size_t works
  * initial ones); after that, g applies from the next step on. */
 LBM_API lbm_status lbm_set_force(lbm_sim *s, int32_t kind, const double *g, int32_t axis, int64_t len);
 
-/* Advance nsteps (>= 0) time steps of eq. (lbm); asynchronous. */
+/* Advance nsteps (>= 0) time steps of eq. (lbm); asynchronous.  If a launch
+ * fails (LBM_EDEVICE), the steps enqueued before it still run and are counted
+ * in lbm_step_count. */
 LBM_API lbm_status lbm_step(lbm_sim *s, int64_t nsteps);
 
 /* Physical moments at the current step, eq. (rut1) with the mid-point shift:
@@ -284,7 +286,8 @@ LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t cou
  * step, on the batch's stream.  The library does not order that stream with the members'
  * own streams: work queued on a member's stream must be complete (or ordered
  * with events) before, and later work on it must wait for the batch's stream
- * (the Python binding does both). */
+ * (the Python binding does both).  If a launch fails (LBM_EDEVICE), the steps
+ * enqueued before it still run and are counted in every member's state. */
 LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
 /* Launch shape of the multi-grid kernel (an implementation choice).  threads: threads per block, 64, 128
@@ -309,7 +312,8 @@ LBM_API void lbm_batch_destroy(lbm_batch *b);
 LBM_API lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph **out);
 
 /* Replay the captured steps of eq. (lbm) `repeats` times (asynchronous on the
- * stream). */
+ * stream).  If a replay fails to launch (LBM_EDEVICE), the replays enqueued
+ * before it still run and are counted. */
 LBM_API lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats);
 
 /* Housekeeping; NULL-safe. */

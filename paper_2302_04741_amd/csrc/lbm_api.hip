@@ -214,9 +214,9 @@ hipError_t launch_one_step(const lbm_sim *s, int cur)
 
 // Enqueues nsteps steps of the state held in pop[cur] (with plates, its partial
 // sums must be current); on return cur names the buffer holding the advanced
-// state and done the steps enqueued (all of them unless a launch failed).  Small grids take the resident kernel, many steps
-// per launch in chunks that keep every launch short; the others one launch (or
-// three, with plates) per step.
+// state and done the steps enqueued (all of them unless a launch failed).
+// Grids within the resident limit take the resident kernel, many steps per
+// launch in chunks that keep every launch short; the others one launch per step.
 hipError_t launch_steps(const lbm_sim *s, int &cur, int64_t nsteps, int64_t &done)
 {
     done = 0;
@@ -656,11 +656,13 @@ hipError_t batch_wall_densities(lbm_batch *b)
     return hipSuccess;
 }
 
-lbm_status batch_launch(lbm_batch *b, int64_t nsteps)
+// Enqueues nsteps batch steps; done is the number enqueued (all of them unless
+// a launch failed).
+lbm_status batch_launch(lbm_batch *b, int64_t nsteps, int64_t &done)
 {
     const lbm_sim *s0 = b->sims[0];
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int parity = int((b->steps_done + k) & 1);
+    for (done = 0; done < nsteps; ++done) {
+        const int parity = int((b->steps_done + done) & 1);
         const BatchLaunch bl{b->begin,  b->table,   int(b->sims.size()), b->ntiles, parity,
                              b->threads, b->blocks, b->stream,           b->walls};
         hipError_t e = launch_multi_step(s0->p.lattice, s0->p.storage, s0->eq, s0->p.force_order,
@@ -800,12 +802,13 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     TraceRange range("lbm_batch_step");
     hipError_t e = batch_wall_densities(b);
     if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
-    st = batch_launch(b, nsteps);
+    int64_t done = 0;
+    st = batch_launch(b, nsteps, done);
+    batch_advance(b, done);  // the steps enqueued before a failed launch still run
     if (st != LBM_OK) {
         for (lbm_sim *s : b->sims) s->wall_fresh = false;
         return st;
     }
-    batch_advance(b, nsteps);
     return ok();
 }
 
@@ -875,7 +878,8 @@ lbm_status lbm_graph_create(lbm_sim *s, lbm_batch *b, int64_t nsteps, lbm_graph 
         hipError_t el = launch_steps(s, cur, nsteps, done);
         if (el != hipSuccess) st = dev_fail(el, "step launch during capture");
     } else {
-        st = batch_launch(b, nsteps);
+        int64_t done = 0;
+        st = batch_launch(b, nsteps, done);
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(stream, &graph);
@@ -914,16 +918,18 @@ lbm_status lbm_graph_launch(lbm_graph *g, int64_t repeats)
         hipError_t e = g->s ? wall_densities(g->s) : batch_wall_densities(g->b);
         if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     }
-    for (int64_t r = 0; r < repeats; ++r) {
-        hipError_t e = hipGraphLaunch(g->exec, g->stream);
-        if (e != hipSuccess) return dev_fail(e, "graph launch");
-    }
-    const int64_t n = g->nsteps * repeats;  // even: buffers end where they started
+    int64_t r = 0;
+    hipError_t e = hipSuccess;
+    for (; r < repeats && e == hipSuccess; ++r) e = hipGraphLaunch(g->exec, g->stream);
+    if (e != hipSuccess) --r;  // the failed replay was not enqueued
+    // the replays enqueued run nsteps (even) steps each: buffers end where they started
+    const int64_t n = g->nsteps * r;
     if (g->s) {
         g->s->step += n;
     } else {
         batch_advance(g->b, n);
     }
+    if (e != hipSuccess) return dev_fail(e, "graph launch");
     return ok();
 }
 
