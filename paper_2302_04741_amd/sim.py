@@ -73,6 +73,9 @@ class Sim:
             nbytes = 256
         raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
+        # the kernels use the workspace on the handle's stream: once freed, the
+        # allocator must not hand it out before that stream has finished with it
+        raw.record_stream(self.stream)
         self._raw = raw
         self.workspace_bytes = nbytes
         self._ws_ptr = raw.data_ptr() + off
@@ -251,6 +254,7 @@ class Sim:
 
     def set_stream(self, stream):
         check(load().lbm_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+        self._raw.record_stream(stream)
         self.stream = stream
 
 
@@ -317,6 +321,7 @@ class Batch:
         if nbytes == 0:
             raise ValueError("max_sims out of range")
         raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        raw.record_stream(self.stream)
         self._raw = raw
         ws = raw.data_ptr() + (-raw.data_ptr()) % 256
         h = ctypes.c_void_p()

@@ -86,3 +86,21 @@ def test_batch_members_on_other_streams(sim_mod):
     b.step(5)
     for s, r in zip(sims, refs):
         assert torch.equal(s.get_populations(), r.get_populations())
+
+
+def test_freed_workspace_waits_for_the_handles_stream(sim_mod):
+    """A handle on a side stream, dropped while its steps are still queued: the
+    workspace must not be handed to a new tensor of the caller's stream before
+    those steps are done (else they would write into that tensor)."""
+    wl = shear(512)
+    side = torch.cuda.Stream()
+    s = sim_mod.from_workload(wl, storage="f32", stream=side)
+    torch.cuda.synchronize()
+    nbytes = s._raw.numel()
+    s.step(2000)  # several milliseconds of work queued on the side stream
+    del s
+    t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    t.fill_(7)
+    torch.cuda.synchronize()
+    assert bool((t == 7).all())
+
