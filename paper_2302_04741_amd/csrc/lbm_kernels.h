@@ -9,12 +9,13 @@
 //   heatflux_kernel  q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical f.
 //   totals kernels   FP64 sums of the stored populations in a fixed order.
 //
-// Layout: populations are SoA planes, A[i*N + cell], cell = (z*ny + y)*nx + x,
-// holding the deviations h_i = f~_i - w_i rho0 (scaled by 2^k_i for F16).
+// Layout: populations are SoA planes, A[i*P + (z*ny + y)*px + x], rows padded
+// to px = nx rounded up to 64 values (P = px*ny*nz), holding the deviations
+// h_i = f~_i - w_i rho0 (scaled by 2^k_i for F16); the padding is never read.
 // The stored state is post-collision ("pull" layout): the pre-collision value
-// of velocity i at cell x is A[i*N + (x - c_i mod L)].  A step reads every
-// element of A exactly once (a permutation per plane) and writes every element
-// of B exactly once, at the thread's own cell.
+// of velocity i at cell x is plane i at x - c_i (periodic).  A step reads every
+// grid element of A exactly once (a permutation per plane) and writes every
+// grid element of B exactly once, at the thread's own cell.
 #pragma once
 
 #include "lbm_internal.h"
