@@ -4,6 +4,7 @@
   that turns eq. (an) into eq. (an1)): exact through degree 9 (D2Q37) and 7
   (D3Q39), inexact one degree higher.
 * The D2Q37 lattice constant printed in the paper's Sec. 3 (golden file).
+* The D3Q39 weights against the published E^7_{3,39} rule (golden file).
 * Hermite tensors of the oracle against their explicit closed forms and against
   the orthogonality relation they must satisfy under an exact rule.
 """
@@ -72,6 +73,34 @@ def test_d3q39_scale_is_sqrt_three_halves(oracle_mod):
     assert abs(r * r - 1.5) < 1e-15
     rest = w[np.all(c == 0, axis=1)][0]
     assert abs(rest - 1.0 / 12.0) < 1e-16
+
+
+def test_d3q39_weights_match_the_published_rule(oracle_mod):
+    """Every shell weight of the derived D3Q39 rule equals the published
+    E^7_{3,39} table (golden file, exact fractions), and so does r^2."""
+    from fractions import Fraction
+
+    shells = {}
+    r2 = None
+    with open(os.path.join(GOLDEN, "d3q39_weights.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            if f[0] == "r2":
+                r2 = float(Fraction(f[1]))
+            else:
+                shells[tuple(int(v) for v in f[:3])] = (int(f[3]), float(Fraction(f[4])))
+    c, w, r, _ = oracle_mod.lattice(1)
+    assert abs(r * r - r2) < 1e-15
+    seen = {}
+    for v, wv in zip(c, w):
+        gen = tuple(sorted((abs(int(a)) for a in v[:3]), reverse=True))
+        assert gen in shells, gen
+        assert abs(wv - shells[gen][1]) <= 1e-15 * shells[gen][1], (gen, wv)
+        seen[gen] = seen.get(gen, 0) + 1
+    assert seen == {g: n for g, (n, _) in shells.items()}
+    assert abs(sum(n * wt for n, wt in shells.values()) - 1.0) < 1e-15
 
 
 @pytest.mark.parametrize("lat", [0, 1])
