@@ -4,7 +4,8 @@
   that turns eq. (an) into eq. (an1)): exact through degree 9 (D2Q37) and 7
   (D3Q39), inexact one degree higher.
 * The D2Q37 lattice constant printed in the paper's Sec. 3 (golden file).
-* The D3Q39 weights against the published E^7_{3,39} rule (golden file).
+* The D2Q37 and D3Q39 weights against the published E^9_{2,37} and E^7_{3,39}
+  rules (golden files).
 * Hermite tensors of the oracle against their explicit closed forms and against
   the orthogonality relation they must satisfy under an exact rule.
 """
@@ -101,6 +102,31 @@ def test_d3q39_weights_match_the_published_rule(oracle_mod):
         seen[gen] = seen.get(gen, 0) + 1
     assert seen == {g: n for g, (n, _) in shells.items()}
     assert abs(sum(n * wt for n, wt in shells.values()) - 1.0) < 1e-15
+
+
+def test_d2q37_weights_match_the_published_rule(oracle_mod):
+    """Every shell weight and the scale r of the derived D2Q37 rule equal the
+    23-digit published E^9_{2,37} values (golden file) to FP64 rounding."""
+    shells = {}
+    r_pub = None
+    with open(os.path.join(GOLDEN, "d2q37_weights.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            if f[0] == "r":
+                r_pub = float(f[1])
+            else:
+                shells[(int(f[0]), int(f[1]))] = (int(f[2]), float(f[3]))
+    c, w, r, _ = oracle_mod.lattice(0)
+    assert abs(r - r_pub) <= 4e-16 * r_pub
+    seen = {}
+    for v, wv in zip(c, w):
+        gen = tuple(sorted((abs(int(a)) for a in v[:2]), reverse=True))
+        assert gen in shells, gen
+        assert abs(wv - shells[gen][1]) <= 1e-15 * shells[gen][1], (gen, wv)
+        seen[gen] = seen.get(gen, 0) + 1
+    assert seen == {g: n for g, (n, _) in shells.items()}
 
 
 @pytest.mark.parametrize("lat", [0, 1])
