@@ -6,7 +6,9 @@ periodic grid, Kolmogorov force g_x = 1e-5 sin(2 pi z/256), rho = 1,
 theta = 1 + 0.05 sin(2 pi y/256), seeded random-phase velocity perturbation of
 RMS 1e-3 per component, tau-hat = 0.8, 3rd-order Hermite equilibrium, full
 force term (a3_F and sigma).  Inputs are synthetic and resident in HBM before
-the timed region.
+the timed region.  `--lattice D2Q37` times the D2Q37 step instead, on the n^2
+thermal shear wave (dtheta 0.1, Ma 0.2, transverse g = 1e-5, 4th-order
+equilibrium).
 
 One "step" is one launch of the fused kernel over the whole grid.  The timed
 region is exactly --steps steps, bracketed by stream synchronisation; its HIP
@@ -154,7 +156,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
 def _oracle_rate(wl, steps: int, nthreads: int = 0):
     import oracle
 
-    sim = oracle.OracleSim(1, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, wl.force_field(),
+    lat = {"D2Q37": 0, "D3Q39": 1}[wl.lattice]
+    sim = oracle.OracleSim(lat, wl.dims, wl.tau_hat, wl.rho, wl.u, wl.theta, wl.force_field(),
                            force_order=wl.force_order, nthreads=nthreads)
     t0 = time.perf_counter()
     sim.step(steps)
@@ -169,9 +172,12 @@ def cpu_baseline(wl, steps: int):
 
     v, dt = _oracle_rate(wl, steps)
     cores = oracle.num_threads()
-    # one host thread, on a 64^3 grid of the same workload (a bounded sample);
-    # the thread count is process-wide, so it is restored afterwards
-    small = workloads.kolmogorov_3d(n=64, tau_hat=wl.tau_hat)
+    # one host thread, on a small grid of the same workload (a bounded sample:
+    # 64^3 or 256^2); the thread count is process-wide, so it is restored afterwards
+    if wl.lattice == "D3Q39":
+        small = workloads.kolmogorov_3d(n=64, tau_hat=wl.tau_hat)
+    else:
+        small = workloads.thermal_shear_2d(n=256, tau_hat=wl.tau_hat)
     v1, dt1 = _oracle_rate(small, 2, nthreads=1)
     oracle.num_threads(cores)
     return {"value": v, "unit": "MLUPS",
@@ -179,8 +185,9 @@ def cpu_baseline(wl, steps: int):
             "sample": "FP64 oracle, full %dx%dx%d grid of the same workload, %d steps "
                       "(%.1f s, init excluded), %s" % (*wl.dims, steps, dt, _cpu_model()),
             "single_thread": {"value": round(v1, 3), "unit": "MLUPS",
-                              "sample": "FP64 oracle, one thread, 64^3 grid of the same "
-                                        "workload, 2 steps (%.1f s)" % dt1}}
+                              "sample": "FP64 oracle, one thread, %s grid of the same "
+                                        "workload, 2 steps (%.1f s)"
+                                        % ("x".join(map(str, small.dims)), dt1)}}
 
 
 def _cpu_model() -> str:
@@ -372,6 +379,9 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid side (default 256)")
+    ap.add_argument("--lattice", default="D3Q39", choices=["D3Q39", "D2Q37"],
+                    help="step workload: D3Q39 Kolmogorov flow (n^3, the headline) or the "
+                         "D2Q37 thermal shear wave (n^2, tau and force of the D2Q37 sweep)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16dev"])
     ap.add_argument("--tau", type=float, default=0.8, help="tau-hat of the step workload")
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
@@ -431,7 +441,10 @@ def main(argv=None) -> int:
     from paper_2302_04741_amd import sim as lbm_sim
     from paper_2302_04741_amd import workloads
 
-    wl = workloads.kolmogorov_3d(n=args.n, tau_hat=args.tau)
+    if args.lattice == "D3Q39":
+        wl = workloads.kolmogorov_3d(n=args.n, tau_hat=args.tau)
+    else:
+        wl = workloads.thermal_shear_2d(n=args.n, tau_hat=args.tau, dtheta=0.1, mach=0.2)
     s = lbm_sim.from_workload(wl, storage=args.storage)
     if args.block:
         s.set_block(args.block)
@@ -494,16 +507,25 @@ def main(argv=None) -> int:
         del a, b
 
     N = wl.ncell
-    Q = 39
+    Q = 39 if args.lattice == "D3Q39" else 37
     sbytes = {"f32": 4, "f64": 8, "f16dev": 2}[args.storage]
     ms_per_step = ms_events / args.steps
     mlups = N / (ms_per_step * 1e-3) / 1e6
     bytes_per_launch = 2.0 * Q * sbytes * N
     achieved = bytes_per_launch / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic() if (args.n == 256 and args.storage == "f32") else None
+    traffic = measured_traffic() if (args.lattice == "D3Q39" and args.n == 256
+                                     and args.storage == "f32") else None
+    if args.lattice == "D3Q39":
+        what = ("D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=%g, "
+                "3rd-order equilibrium, force with a3_F and sigma"
+                % (args.n, args.storage.upper(), args.tau))
+    else:
+        what = ("D2Q37 %d^2 periodic thermal shear wave (dtheta 0.1, Ma 0.2, g = (0, -1e-5)), "
+                "%s deviation storage, tau=%g, 4th-order equilibrium, force with a3_F and "
+                "sigma" % (args.n, args.storage.upper(), args.tau))
 
     out = {
-        "metric": "D3Q39 force-collide-stream MLUPS",
+        "metric": "%s force-collide-stream MLUPS" % args.lattice,
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -516,10 +538,8 @@ def main(argv=None) -> int:
         "dtype": ARITH[args.storage],
         "data": "synthetic",
         "config": {
-            "workload": "D3Q39 %d^3 periodic Kolmogorov flow, %s deviation storage, tau=%g, "
-                        "3rd-order equilibrium, force with a3_F and sigma"
-                        % (args.n, args.storage.upper(), args.tau),
-            "grid": [args.n] * 3,
+            "workload": what,
+            "grid": list(wl.dims),
             "storage": args.storage,
             "block": args.block or "default",
             "parallelism": "single GPU",
