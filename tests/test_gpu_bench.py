@@ -37,6 +37,26 @@ def test_bench_line_fields():
     assert d["repeats"]["count"] == 2
 
 
+def test_bench_line_d2q37():
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        rc = bench.main(["--lattice", "D2Q37", "--n", "256", "--storage", "f64", "--steps", "5",
+                         "--warmup", "2", "--repeats", "1", "--cpu-steps", "1"])
+    assert rc == 0
+    lines = [ln for ln in buf.getvalue().splitlines() if ln.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    assert d["metric"] == "D2Q37 force-collide-stream MLUPS" and d["value"] > 0
+    assert d["config"]["grid"] == [256, 256, 1] and d["dtype"] == "f64"
+    assert d["config"]["workload"].startswith("D2Q37 256^2")
+    r = d["roofline"]
+    # 2 * 37 * 8 bytes per update
+    assert abs(r["achieved"] - 592 * d["value"] / 1e3) < 1e-3 * r["achieved"] + 0.2
+    assert r["traffic"] is None
+    assert d["cpu_baseline"]["kind"] == "oracle" and d["cpu_baseline"]["value"] > 0
+    assert "256x256x1" in d["cpu_baseline"]["single_thread"]["sample"]
+
+
 @pytest.mark.parametrize("storage,floor", [("f32", 0.90), ("f16dev", 0.85)])
 def test_step_stays_near_its_pattern_ceiling(storage, floor):
     """Performance guard, relative to the same box: the fused step on the
