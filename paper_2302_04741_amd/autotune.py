@@ -8,7 +8,8 @@
 Candidates are timed with HIP events on scratch simulations of the same shape
 (smooth synthetic fields; the cost of a step does not depend on the data), so
 tuning never touches a caller's state.  Results are cached in a JSON file
-(``$LBM_AUTOTUNE_CACHE``, default ``~/.cache/paper_2302_04741_amd/autotune.json``).
+(``$LBM_AUTOTUNE_CACHE``, default ``~/.cache/paper_2302_04741_amd/autotune.json``),
+keyed by the GPU architecture and the library version as well as the problem class.
 Every launch shape gives bitwise the same results, so tuning only affects speed.
 """
 from __future__ import annotations
@@ -87,8 +88,21 @@ def _scratch(lattice, dims, storage, eq_order, force_order, seed=0, stream=None)
     return sim.from_workload(wl, storage=storage, stream=stream)
 
 
+def _device_tag() -> str:
+    """The GPU architecture and the library version: tuned shapes are kept per
+    device type and per build of the kernels."""
+    import torch
+
+    from . import _lib
+
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return "%s/%s" % (arch.split(":")[0], _lib.load().lbm_version().decode())
+
+
 def block_key(lattice, storage, eq_order, force_order, dims) -> str:
-    return "block/%s/%s/eq%d/fo%d/%s" % (lattice, storage, eq_order, force_order, grid_class(dims))
+    return "block/%s/%s/%s/eq%d/fo%d/%s" % (_device_tag(), lattice, storage, eq_order,
+                                            force_order, grid_class(dims))
 
 
 def tune_block(lattice: str, dims, storage: str = "f32", eq_order: int = 0, force_order: int = 4,
@@ -115,8 +129,8 @@ def tune_block(lattice: str, dims, storage: str = "f32", eq_order: int = 0, forc
 
 
 def batch_key(lattice, storage, eq_order, force_order, dims_list) -> str:
-    return "batch/%s/%s/eq%d/fo%d/%s" % (lattice, storage, eq_order, force_order,
-                                         batch_class(dims_list))
+    return "batch/%s/%s/%s/eq%d/fo%d/%s" % (_device_tag(), lattice, storage, eq_order,
+                                            force_order, batch_class(dims_list))
 
 
 def tune_batch_launch(lattice: str, dims_list, storage: str = "f32", eq_order: int = 0,

@@ -214,6 +214,8 @@ def test_autotuner_picks_and_caches_launch_shapes(sim_mod, tmp_path, monkeypatch
 
     cache = json.loads((tmp_path / "tune.json").read_text())
     assert len(cache) == 2 and all("ms_per_step" in v for v in cache.values())
+    # kept per device architecture and library build
+    assert all("/gfx950/lbm-gfx950 " in k for k in cache), list(cache)
     # a second call is served from the cache (no timing run)
     assert autotune.tune_batch_launch("D2Q37", dims_list, storage="f32") == launch
     # the tuned shape gives the same populations as the default shape
