@@ -302,6 +302,37 @@ LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t b
  * queued steps. */
 LBM_API void lbm_batch_destroy(lbm_batch *b);
 
+/* Largest member count of lbm_batch_step_noalloc. */
+#define LBM_NOALLOC_MAX_SIMS 256
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): advance `count`
+ * simulations by nsteps (>= 0) steps of eq. (lbm) in the multi-grid kernel of
+ * lbm_batch_step, with no batch handle and no batch workspace.  The tile table
+ * (the scratch of the multi-grid kernel: tile offsets and one descriptor per
+ * member) lives in a fixed device array of the library, sized for
+ * LBM_NOALLOC_MAX_SIMS members (about 51 KB; each device the library runs on
+ * holds one until the process ends).  Every call rewrites that table on
+ * hip_stream with small copy kernels (the descriptors travel as kernel
+ * arguments, so no host buffer must outlive the call), then launches one
+ * multi-grid step per step.
+ *   sims: 1..LBM_NOALLOC_MAX_SIMS distinct handles sharing lattice, storage,
+ *         eq_order and force_order (grids, tau_hat, mu, forces and plates may
+ *         differ); count above the maximum is LBM_EINVAL.  Launch shape: that
+ *         of a default batch (128 threads, one wavefront per 64-cell tile), so
+ *         every member's result is bitwise the one lbm_batch_step gives.
+ *   hip_stream: the stream of every launch (NULL = the null stream); the
+ *         current device must be the members' device.  As with lbm_batch_step,
+ *         work on the members' own streams must be ordered with it by the caller.
+ * No call allocates or frees memory on the device or the host.  The array is
+ * shared by every call on a device and keeps the last call's table: calls that
+ * overlap on one device (different streams, or threads) race and must be
+ * serialised by the caller.  The first call on a device resolves the array's
+ * address (hipGetSymbolAddress); make it once before any graph capture.
+ * Errors: as lbm_batch_step; argument errors leave every member unchanged. */
+LBM_API lbm_status lbm_batch_step_noalloc(lbm_sim *const *sims, int32_t count, int64_t nsteps,
+                                          void *hip_stream);
+
 /* Capture nsteps (even, > 0) steps of eq. (lbm) of one simulation (s) or one
  * batch (b) --
  * exactly one of them non-NULL -- into a HIP graph on its stream, which must

@@ -25,6 +25,7 @@ STORAGES = {"f64": 0, "f32": 1, "f16dev": 2}
 FORCE_KINDS = {"uniform": 0, "axis": 1, "field": 2}
 FLAG_FORCE_FIELD = 1
 FLAG_WALLS = 2
+NOALLOC_MAX_SIMS = 256  # LBM_NOALLOC_MAX_SIMS
 
 #: the C-ABI entry points, in the order include/lbm.h declares them
 API_SYMBOLS = (
@@ -34,7 +35,7 @@ API_SYMBOLS = (
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
     "lbm_set_stream", "lbm_set_block", "lbm_set_resident_limit", "lbm_set_viscosity",
     "lbm_set_walls", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set",
-    "lbm_batch_step", "lbm_batch_set_launch", "lbm_batch_destroy",
+    "lbm_batch_step", "lbm_batch_set_launch", "lbm_batch_destroy", "lbm_batch_step_noalloc",
     "lbm_graph_create", "lbm_graph_launch", "lbm_graph_destroy", "lbm_lattice_table",
     "lbm_version",
 )
@@ -133,6 +134,8 @@ def load() -> ctypes.CDLL:
     L.lbm_batch_set_launch.restype = _i32
     L.lbm_batch_destroy.argtypes = [_vp]
     L.lbm_batch_destroy.restype = None
+    L.lbm_batch_step_noalloc.argtypes = [ctypes.POINTER(_vp), _i32, _i64, _vp]
+    L.lbm_batch_step_noalloc.restype = _i32
     L.lbm_graph_create.argtypes = [_vp, _vp, _i64, ctypes.POINTER(_vp)]
     L.lbm_graph_create.restype = _i32
     L.lbm_graph_launch.argtypes = [_vp, _i64]

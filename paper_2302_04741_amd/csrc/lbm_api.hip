@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -672,6 +673,20 @@ lbm_status batch_launch(lbm_batch *b, int64_t nsteps, int64_t &done)
     return LBM_OK;
 }
 
+// A member's tile-table descriptor; its tiles start at first_tile.
+void fill_tile_sim(TileSim &t, const lbm_sim *s, int64_t first_tile)
+{
+    t.pop[0] = s->pop[0];
+    t.pop[1] = s->pop[1];
+    t.cur = s->cur;
+    t.chunks_x = int32_t((s->p.nx + 63) / 64);
+    t.tile_begin = first_tile;
+    t.gd = s->gd;
+    t.fd = s->fd;
+    t.co = s->co;
+    t.wd = s->wd;
+}
+
 // Build the tile table of `sims` (64-cell tiles) and upload it on
 // the batch's stream (the host staging copy lives in the batch, so the
 // asynchronous copy never reads freed memory).
@@ -692,18 +707,9 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
             s->p.force_order != s0->p.force_order)
             return fail(LBM_EINVAL,
                         "batch members must share lattice, storage, eq_order and force_order");
-        TileSim &t = tab[k];
-        t.pop[0] = s->pop[0];
-        t.pop[1] = s->pop[1];
-        t.cur = s->cur;
-        t.chunks_x = int32_t((s->p.nx + 63) / 64);
-        t.tile_begin = tiles;
-        t.gd = s->gd;
-        t.fd = s->fd;
-        t.co = s->co;
-        t.wd = s->wd;
+        fill_tile_sim(tab[k], s, tiles);
         begin[k] = tiles;
-        tiles += int64_t(t.chunks_x) * s->p.ny * s->p.nz;
+        tiles += int64_t(tab[k].chunks_x) * s->p.ny * s->p.nz;
     }
     begin[count] = tiles;
     // wait for the previous upload before replacing its staging copy
@@ -832,6 +838,147 @@ void lbm_batch_destroy(lbm_batch *b)
     // the last tile-table upload reads the host staging copy owned here
     if (b->upload_pending) (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batch step without a workspace: the tile table in a fixed device array
+// ---------------------------------------------------------------------------
+namespace {
+// members per table-fill launch: their descriptors travel as kernel arguments
+constexpr int NOALLOC_CHUNK = 16;
+constexpr size_t NOALLOC_BEGIN_BYTES = (size_t(LBM_NOALLOC_MAX_SIMS + 1) * 8 + ALIGN - 1) /
+                                       ALIGN * ALIGN;
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    NOALLOC_BEGIN_BYTES + size_t(LBM_NOALLOC_MAX_SIMS) * sizeof(TileSim);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Members first .. first + n - 1 of a tile table; `last` also sets the end of
+// the list, begin[first + n] = end.
+struct TableChunk {
+    int32_t first, n, last;
+    int64_t end;
+    int64_t begin[NOALLOC_CHUNK];
+    TileSim sims[NOALLOC_CHUNK];
+};
+static_assert(sizeof(TableChunk) <= 4000, "kernel arguments are limited to 4 KiB");
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+// The tile table of lbm_batch_step_noalloc: tile offsets
+// (LBM_NOALLOC_MAX_SIMS + 1 int64, padded to 256 bytes), then one TileSim per
+// member.  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+__global__ void __launch_bounds__(64) table_fill_kernel(TableChunk c, unsigned char *base)
+{
+    int64_t *begin = reinterpret_cast<int64_t *>(base);
+    TileSim *tab = reinterpret_cast<TileSim *>(base + NOALLOC_BEGIN_BYTES);
+    const int t = int(threadIdx.x);
+    if (t < c.n) {
+        begin[c.first + t] = c.begin[t];
+        tab[c.first + t] = c.sims[t];
+    }
+    if (t == 0 && c.last) begin[c.first + c.n] = c.end;
+}
+
+namespace {
+// Device address of `scratch` on the current device, resolved once per device.
+hipError_t scratch_address(unsigned char **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_step_noalloc(lbm_sim *const *sims, int32_t count, int64_t nsteps,
+                                  void *hip_stream)
+{
+    if (!sims) return fail(LBM_EINVAL, "sims is NULL");
+    if (count < 1 || count > LBM_NOALLOC_MAX_SIMS)
+        return fail(LBM_EINVAL,
+                    "count must be in [1, %d]: the fixed tile table holds %d members (got %d)",
+                    LBM_NOALLOC_MAX_SIMS, LBM_NOALLOC_MAX_SIMS, count);
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    for (int32_t k = 0; k < count; ++k) {
+        const lbm_sim *s = sims[k];
+        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
+        const lbm_sim *s0 = sims[0];
+        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
+            s->p.force_order != s0->p.force_order)
+            return fail(LBM_EINVAL,
+                        "batch members must share lattice, storage, eq_order and force_order");
+    }
+    if (nsteps == 0) return ok();
+    unsigned char *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return dev_fail(e, "tile table address");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    TraceRange range("lbm_batch_step_noalloc");
+    for (int32_t k = 0; k < count; ++k) {
+        e = wall_densities(sims[k], stream);
+        if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
+    }
+    // the tile table, NOALLOC_CHUNK members per fill launch
+    int64_t tiles = 0;
+    bool walls = false;
+    for (int32_t first = 0; first < count; first += NOALLOC_CHUNK) {
+        TableChunk c;
+        std::memset(&c, 0, sizeof c);
+        c.first = first;
+        c.n = std::min<int32_t>(NOALLOC_CHUNK, count - first);
+        for (int32_t k = 0; k < c.n; ++k) {
+            const lbm_sim *s = sims[first + k];
+            fill_tile_sim(c.sims[k], s, tiles);
+            c.begin[k] = tiles;
+            tiles += int64_t(c.sims[k].chunks_x) * s->p.ny * s->p.nz;
+            walls = walls || s->wd.on;
+        }
+        c.last = first + c.n == count;
+        c.end = tiles;
+        hipLaunchKernelGGL(table_fill_kernel, dim3(1), dim3(64), 0, stream, c, base);
+        e = hipGetLastError();
+        if (e != hipSuccess) return dev_fail(e, "tile table fill launch");
+    }
+    const lbm_sim *s0 = sims[0];
+    const int64_t *begin = reinterpret_cast<const int64_t *>(base);
+    const TileSim *table = reinterpret_cast<const TileSim *>(base + NOALLOC_BEGIN_BYTES);
+    int64_t done = 0;
+    for (; done < nsteps; ++done) {
+        const BatchLaunch bl{begin,  table, int(count), tiles, int(done & 1), BATCH_DEFAULT_THREADS,
+                             0,      stream, walls};
+        e = launch_multi_step(s0->p.lattice, s0->p.storage, s0->eq, s0->p.force_order, bl);
+        if (e != hipSuccess) break;
+    }
+    // the steps enqueued before a failed launch still run
+    for (int32_t k = 0; k < count; ++k) {
+        sims[k]->cur ^= int(done & 1);
+        sims[k]->step += done;
+        if (e != hipSuccess) sims[k]->wall_fresh = false;
+    }
+    if (e != hipSuccess) return dev_fail(e, "multi-grid step launch");
+    return ok();
 }
 
 // ---------------------------------------------------------------------------

@@ -376,3 +376,25 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_step_noalloc(sims, n: int = 1, stream=None):
+    """Advance `sims` (1..256 Sims sharing lattice, storage and orders) by n
+    steps of the multi-grid kernel without a batch handle or workspace: the
+    tile table lives in the library's fixed device array
+    (lbm_batch_step_noalloc; calls that overlap on one device race).  Runs on
+    `stream` (default: the current stream), ordered after the members' own
+    streams and before their later work."""
+    torch = _torch()
+    if not sims:
+        raise ValueError("no simulations")
+    stream = stream if stream is not None else torch.cuda.current_stream(sims[0].device)
+    others = {s.stream.cuda_stream: s.stream for s in sims
+              if s.stream.cuda_stream != stream.cuda_stream}
+    for st in others.values():
+        stream.wait_stream(st)
+    arr = (ctypes.c_void_p * len(sims))(*[s.handle.value for s in sims])
+    check(load().lbm_batch_step_noalloc(arr, len(sims), int(n),
+                                        ctypes.c_void_p(stream.cuda_stream)))
+    for st in others.values():
+        st.wait_stream(stream)

@@ -255,3 +255,18 @@ def test_largest_plane(lib, storage, sbytes):
     padded = params(lattice="D3Q39", dims=(1000, ny, nz), storage=storage)
     assert 1000 * ny * nz * sbytes < (1 << 32)
     assert _lib.workspace_bytes(padded) == 0
+
+
+def test_batch_step_noalloc_argument_checks(lib):
+    """Argument errors of the no-allocation batch step are found before any
+    member is read or any HIP call is made."""
+    cap = _lib.NOALLOC_MAX_SIMS
+    step = lib.lbm_batch_step_noalloc
+    assert step(None, 1, 1, None) == _lib.LBM_EINVAL
+    arr = (ctypes.c_void_p * (cap + 1))()
+    assert step(arr, 0, 1, None) == _lib.LBM_EINVAL
+    assert step(arr, cap + 1, 1, None) == _lib.LBM_EINVAL
+    assert "[1, %d]" % cap in lib.lbm_last_error().decode()
+    assert step(arr, 1, -1, None) == _lib.LBM_EINVAL
+    assert step(arr, 1, 1, None) == _lib.LBM_EINVAL  # a NULL member
+    assert "NULL" in lib.lbm_last_error().decode()
