@@ -20,6 +20,13 @@ update is one read and one write of every population, 2 * Q * s = 312 bytes
 per cell.  `traffic` is the measured HBM traffic per launch from the committed
 rocprofv3 counter summary, valid only while the kernel sources are unchanged.
 
+Serving (the latency half of the metric, `serving` in the same line): the
+stream of 256 D2Q37 FP32 requests (Poisson arrivals at 20/s, L ~ U{64..1024},
+2000 steps each) served by continuous batching under a 1 GiB HBM budget: p50
+and p99 completion latency of the real-time run, and the aggregate MLUPS of the
+real-time run, of a run with every request queued at t = 0 and of the same
+requests solved one after another with the single-grid kernel.
+
 CPU baseline: the FP64 CPU oracle (as it stands) on the same workload at full
 size for a bounded number of steps, on the host's cores.
 """
@@ -50,13 +57,20 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "step_d3q39_f32_256cube_pmc.txt")
 _COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
 
 
+# the sources the D3Q39 FP32 step kernel is compiled from (its translation unit
+# and every header it includes); host code and the other kernels' units are not
+# part of it
+STEP_KERNEL_SOURCES = ("fastdiv.h", "lattice_tables.h", "lbm_internal.h", "lbm_kernels.h",
+                       "lbm_launch.h", "step_d3q39_f32.hip")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources that make up the library, comments and blank
+    """Hash of the sources of the measured step kernel, comments and blank
     lines left out (an edit of a comment does not change what was measured)."""
     csrc = os.path.join(ROOT, "paper_2302_04741_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
+        if name in STEP_KERNEL_SOURCES:
             with open(os.path.join(csrc, name), encoding="utf-8") as fh:
                 code = _COMMENT.sub("", fh.read())
             lines = [ln.rstrip() for ln in code.splitlines() if ln.strip()]
@@ -290,49 +304,64 @@ def bench_batch(args) -> dict:
     }
 
 
-def bench_serve(args) -> dict:
-    """The serving stream: 256 D2Q37 requests, Poisson arrivals at 20/s, 2000
-    steps each, served by continuous batching under an HBM budget; latency run
-    in real time, then a throughput run with every request queued at t = 0,
-    and the same requests solved one after another with the single-grid
+def serve_stream(args) -> dict:
+    """The serving stream: --count D2Q37 requests, Poisson arrivals at --rate/s,
+    --req-steps steps each, served by continuous batching under an HBM budget:
+    a latency run in real time, a throughput run with every request queued at
+    t = 0, and the same requests solved one after another with the single-grid
     kernel."""
     from paper_2302_04741_amd import serve
 
     reqs = serve.make_requests(n=args.count, rate=args.rate, seed=args.seed, steps=args.req_steps)
     budget = int(args.budget_gib * (1 << 30))
-    srv = serve.Server(storage=args.storage, max_slots=args.slots, budget_bytes=budget,
-                       chunk_steps=args.chunk)
-    live = srv.run(reqs, realtime=True)
+
+    def server():
+        return serve.Server(storage=args.storage, max_slots=args.slots, budget_bytes=budget,
+                            chunk_steps=args.chunk, launch=args.launch)
+
+    live = server().run(reqs, realtime=True)
     print("serve: real-time run done in %.1f s" % live["wall_s"], file=sys.stderr, flush=True)
-    thr = serve.Server(storage=args.storage, max_slots=args.slots, budget_bytes=budget,
-                       chunk_steps=args.chunk).run(reqs, realtime=False)
+    thr = server().run(reqs, realtime=False)
     print("serve: queued run done in %.1f s" % thr["wall_s"], file=sys.stderr, flush=True)
     seq = serve.run_sequential(reqs, storage=args.storage)
     print("serve: sequential run done in %.1f s" % seq["wall_s"], file=sys.stderr, flush=True)
     return {
-        "metric": "served completion latency p50/p99 and aggregate MLUPS",
-        "value": round(live["p99_latency_s"], 4),
-        "unit": "s (p99 latency)",
-        "n_gpus": 1,
-        "higher_is_better": False,
-        "dtype": ARITH[args.storage],
-        "data": "synthetic",
-        "config": {"workload": "%d D2Q37 requests, Poisson %.0f/s (seed %d), L ~ U{64..1024}, "
-                               "%d steps each, %s storage, %d slots, %.1f GiB budget, "
-                               "%d-step chunks"
-                               % (args.count, args.rate, args.seed, args.req_steps,
-                                  args.storage.upper(), args.slots, args.budget_gib, args.chunk)},
+        "workload": "%d D2Q37 requests, Poisson %.0f/s (seed %d), L ~ U{64..1024}, %d steps "
+                    "each, %s storage, %d slots, %.1f GiB budget, %d-step chunks"
+                    % (args.count, args.rate, args.seed, args.req_steps, args.storage.upper(),
+                       args.slots, args.budget_gib, args.chunk),
         "p50_latency_s": round(live["p50_latency_s"], 4),
         "p99_latency_s": round(live["p99_latency_s"], 4),
+        "requests": live["requests"],
         "failed": live["failed"],
         "max_concurrent": live["max_concurrent"],
         "live_wall_s": round(live["wall_s"], 3),
         "live_aggregate_mlups": round(live["aggregate_mlups"], 1),
         "queued_aggregate_mlups": round(thr["aggregate_mlups"], 1),
+        "queued_wall_s": round(thr["wall_s"], 3),
         "queued_max_concurrent": thr["max_concurrent"],
         "queued_failed": thr["failed"],
         "sequential_aggregate_mlups": round(seq["aggregate_mlups"], 1),
+        "sequential_wall_s": round(seq["wall_s"], 3),
+        "launch": {"live": live["launches"], "queued": thr["launches"]},
     }
+
+
+def bench_serve(args) -> dict:
+    """The serving stream as its own bench line (p99 latency as the value)."""
+    sv = serve_stream(args)
+    out = {
+        "metric": "served completion latency p50/p99 and aggregate MLUPS",
+        "value": sv["p99_latency_s"],
+        "unit": "s (p99 latency)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": ARITH[args.storage],
+        "data": "synthetic",
+        "config": {"workload": sv.pop("workload")},
+    }
+    out.update(sv)
+    return out
 
 
 def bench_channel(args) -> dict:
@@ -410,7 +439,14 @@ def main(argv=None) -> int:
     ap.add_argument("--req-steps", type=int, default=2000, help="serve: steps per request")
     ap.add_argument("--slots", type=int, default=64, help="serve: concurrent requests")
     ap.add_argument("--budget-gib", type=float, default=1.0, help="serve: HBM budget")
-    ap.add_argument("--chunk", type=int, default=100, help="serve: steps per batched chunk")
+    ap.add_argument("--chunk", type=int, default=25, help="serve: steps per batched chunk")
+    ap.add_argument("--launch", default="default", choices=["default", "tuned"],
+                    help="serve: multi-grid launch shape (default: 128 threads, one wavefront "
+                         "per tile; tuned: the autotuner's choice per batch class)")
+    ap.add_argument("--serve-count", type=int, default=256,
+                    help="step: requests of the serving stream in the default line")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="step: leave out the serving-stream figures of the default line")
     args = ap.parse_args(argv)
 
     if args.summarize_pmc:
@@ -571,9 +607,14 @@ def main(argv=None) -> int:
                           "median_mlups": round(N / (med * 1e-3) / 1e6, 1),
                           "min_mlups": round(N / (max(rep_ms) * 1e-3) / 1e6, 1),
                           "max_mlups": round(N / (min(rep_ms) * 1e-3) / 1e6, 1)}
+    del s, rho, u, th
+    torch.cuda.empty_cache()
+    if not args.no_serve and args.lattice == "D3Q39":
+        # the latency half of the metric: the serving stream (D2Q37 FP32 requests)
+        sargs = argparse.Namespace(**vars(args))
+        sargs.storage, sargs.count = "f32", args.serve_count
+        out["serving"] = serve_stream(sargs)
     if args.cpu_steps > 0:
-        del s, rho, u, th
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0

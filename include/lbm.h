@@ -172,6 +172,13 @@ LBM_API const char *lbm_last_error(void);
  * any sum is not finite. */
 LBM_API lbm_status lbm_totals(lbm_sim *s, double *out);
 
+/* The same sums as lbm_totals, written to device memory and not waited for:
+ * out_dev receives D+2 doubles on the handle's stream (asynchronous, no
+ * finiteness check), so that a caller can check many simulations without
+ * stalling the device (a serving loop reads them back once their step work is
+ * done).  LBM_EINVAL on a NULL handle or pointer. */
+LBM_API lbm_status lbm_totals_device(lbm_sim *s, double *out_dev);
+
 /* Heat flux q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical
  * distribution f = f0 + (1 - 1/(2 tau-hat)) (f~ - f0 + F/2) at the current
  * step (the quantity q_err of Sec. 2 refers to).  q: D*N device doubles. */
@@ -276,8 +283,9 @@ LBM_API size_t lbm_batch_workspace_bytes(int32_t max_sims);
 LBM_API lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_bytes,
                                     void *hip_stream, lbm_batch **out);
 
-/* Set the members (1..max_sims handles, no duplicates) and upload the tile
- * table on the batch's stream.  Call again after a member was stepped or had
+/* Set the members (1..max_sims handles, no duplicates) and write the tile
+ * table on the batch's stream (small copy kernels; the call does not wait for
+ * the device).  Call again after a member was stepped or had
  * its force changed outside the batch (lbm_batch_step refuses stale tables).
  * Destroying a member leaves the batch unusable until the next lbm_batch_set. */
 LBM_API lbm_status lbm_batch_set(lbm_batch *b, lbm_sim *const *sims, int32_t count);
@@ -297,9 +305,8 @@ LBM_API lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
  * captured before must be captured again. */
 LBM_API lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks);
 
-/* Housekeeping; NULL-safe; does not free the workspace.  Waits only for the
- * last tile-table upload (it reads host memory owned by the batch), not for
- * queued steps. */
+/* Housekeeping; NULL-safe; does not free the workspace and does not wait for
+ * queued steps (the caller keeps the workspace until the stream has run them). */
 LBM_API void lbm_batch_destroy(lbm_batch *b);
 
 /* Largest member count of lbm_batch_step_noalloc. */

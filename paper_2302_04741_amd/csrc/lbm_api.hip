@@ -432,6 +432,16 @@ lbm_status lbm_totals(lbm_sim *s, double *out)
     return ok();
 }
 
+lbm_status lbm_totals_device(lbm_sim *s, double *out_dev)
+{
+    if (!s) return fail(LBM_EINVAL, "handle is NULL");
+    if (!out_dev) return fail(LBM_EINVAL, "out_dev is NULL");
+    hipError_t e = launch_totals(s->p.lattice, s->p.storage, s->pop[s->cur], s->partials,
+                                 out_dev, s->gd, s->co, s->stream);
+    if (e != hipSuccess) return dev_fail(e, "totals kernel launch");
+    return ok();
+}
+
 lbm_status lbm_heat_flux(lbm_sim *s, double *q)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
@@ -597,6 +607,97 @@ const char *lbm_version(void) { return "lbm-gfx950 0.4.0"; }
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// tile tables of the multi-grid step, written on the device by small copy
+// kernels whose arguments carry the descriptors (no host staging buffer has to
+// outlive the call, and nothing waits for the device)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int TABLE_CHUNK = 16;  // members per fill launch: kernel arguments <= 4 KiB
+
+// Members first .. first + n - 1 of a tile table; `last` also sets the end of
+// the list, begin[first + n] = end.
+struct TableChunk {
+    int32_t first, n, last;
+    int64_t end;
+    int64_t begin[TABLE_CHUNK];
+    TileSim sims[TABLE_CHUNK];
+};
+static_assert(sizeof(TableChunk) <= 4000, "kernel arguments are limited to 4 KiB");
+}  // namespace
+
+__global__ void __launch_bounds__(64) table_fill_kernel(TableChunk c, int64_t *begin, TileSim *tab)
+{
+    const int t = int(threadIdx.x);
+    if (t < c.n) {
+        begin[c.first + t] = c.begin[t];
+        tab[c.first + t] = c.sims[t];
+    }
+    if (t == 0 && c.last) begin[c.first + c.n] = c.end;
+}
+
+namespace {
+// Members of one multi-grid launch: non-NULL, distinct, same kernel variant.
+lbm_status check_members(lbm_sim *const *sims, int32_t count)
+{
+    for (int32_t k = 0; k < count; ++k) {
+        const lbm_sim *s = sims[k];
+        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
+        const lbm_sim *s0 = sims[0];
+        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
+            s->p.force_order != s0->p.force_order)
+            return fail(LBM_EINVAL,
+                        "batch members must share lattice, storage, eq_order and force_order");
+    }
+    return LBM_OK;
+}
+
+// A member's tile-table descriptor; its tiles start at first_tile.
+void fill_tile_sim(TileSim &t, const lbm_sim *s, int64_t first_tile)
+{
+    t.pop[0] = s->pop[0];
+    t.pop[1] = s->pop[1];
+    t.cur = s->cur;
+    t.chunks_x = int32_t((s->p.nx + 63) / 64);
+    t.tile_begin = first_tile;
+    t.gd = s->gd;
+    t.fd = s->fd;
+    t.co = s->co;
+    t.wd = s->wd;
+}
+
+// Write the tile table of `sims` (64-cell tiles) to begin[count + 1] and
+// tab[count] on `stream`; tiles = the length of the list, walls = some member
+// has plates.
+hipError_t upload_table(lbm_sim *const *sims, int32_t count, int64_t *begin, TileSim *tab,
+                        hipStream_t stream, int64_t &tiles, bool &walls)
+{
+    tiles = 0;
+    walls = false;
+    for (int32_t first = 0; first < count; first += TABLE_CHUNK) {
+        TableChunk c;
+        std::memset(&c, 0, sizeof c);
+        c.first = first;
+        c.n = std::min<int32_t>(TABLE_CHUNK, count - first);
+        for (int32_t k = 0; k < c.n; ++k) {
+            const lbm_sim *s = sims[first + k];
+            fill_tile_sim(c.sims[k], s, tiles);
+            c.begin[k] = tiles;
+            tiles += int64_t(c.sims[k].chunks_x) * s->p.ny * s->p.nz;
+            walls = walls || s->wd.on;
+        }
+        c.last = first + c.n == count;
+        c.end = tiles;
+        hipLaunchKernelGGL(table_fill_kernel, dim3(1), dim3(64), 0, stream, c, begin, tab);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
+
 struct lbm_batch {
     int32_t max_sims;
     hipStream_t stream;
@@ -606,13 +707,11 @@ struct lbm_batch {
     std::vector<lbm_sim *> sims;
     std::vector<int64_t> step_at_set;  // members' step counts when the table was built
     std::vector<int64_t> gen_at_set;   // members' launch-argument generations then
-    std::vector<char> host;            // staging copy of the uploaded table
     int64_t generation;                // bumped whenever the table or launch shape changes
     int64_t steps_done;                // batch steps since the table was built
     int64_t ntiles;
     int threads;     // threads per block (tiles of 64 cells, one per wavefront)
     int64_t blocks;  // 0: one block per tile
-    bool upload_pending;  // an asynchronous upload may still read `host`
     bool walls;           // some member has plates
 };
 
@@ -673,56 +772,16 @@ lbm_status batch_launch(lbm_batch *b, int64_t nsteps, int64_t &done)
     return LBM_OK;
 }
 
-// A member's tile-table descriptor; its tiles start at first_tile.
-void fill_tile_sim(TileSim &t, const lbm_sim *s, int64_t first_tile)
-{
-    t.pop[0] = s->pop[0];
-    t.pop[1] = s->pop[1];
-    t.cur = s->cur;
-    t.chunks_x = int32_t((s->p.nx + 63) / 64);
-    t.tile_begin = first_tile;
-    t.gd = s->gd;
-    t.fd = s->fd;
-    t.co = s->co;
-    t.wd = s->wd;
-}
-
-// Build the tile table of `sims` (64-cell tiles) and upload it on
-// the batch's stream (the host staging copy lives in the batch, so the
-// asynchronous copy never reads freed memory).
+// Set the members and write their tile table into the batch workspace on the
+// batch's stream (asynchronous: no host buffer has to outlive the call).
 lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
 {
-    const size_t off = batch_begin_bytes(b->max_sims);
-    std::vector<char> host(off + size_t(count) * sizeof(TileSim), 0);
-    int64_t *begin = reinterpret_cast<int64_t *>(host.data());
-    TileSim *tab = reinterpret_cast<TileSim *>(host.data() + off);
+    lbm_status st = check_members(sims, count);
+    if (st != LBM_OK) return st;
     int64_t tiles = 0;
-    for (int32_t k = 0; k < count; ++k) {
-        const lbm_sim *s = sims[k];
-        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
-        for (int32_t j = 0; j < k; ++j)
-            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
-        const lbm_sim *s0 = sims[0];
-        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
-            s->p.force_order != s0->p.force_order)
-            return fail(LBM_EINVAL,
-                        "batch members must share lattice, storage, eq_order and force_order");
-        fill_tile_sim(tab[k], s, tiles);
-        begin[k] = tiles;
-        tiles += int64_t(tab[k].chunks_x) * s->p.ny * s->p.nz;
-    }
-    begin[count] = tiles;
-    // wait for the previous upload before replacing its staging copy
-    if (b->upload_pending) {
-        hipError_t e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) return dev_fail(e, "stream synchronize");
-        b->upload_pending = false;
-    }
-    b->host.swap(host);
-    hipError_t e = hipMemcpyAsync(b->ws, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
-                                  b->stream);
-    if (e != hipSuccess) return dev_fail(e, "tile table upload");
-    b->upload_pending = true;
+    bool walls = false;
+    hipError_t e = upload_table(sims, count, b->begin, b->table, b->stream, tiles, walls);
+    if (e != hipSuccess) return dev_fail(e, "tile table fill launch");
     b->sims.assign(sims, sims + count);
     b->step_at_set.clear();
     b->gen_at_set.clear();
@@ -733,8 +792,7 @@ lbm_status batch_build(lbm_batch *b, lbm_sim *const *sims, int32_t count)
     b->steps_done = 0;
     b->generation++;
     b->ntiles = tiles;
-    b->walls = false;
-    for (lbm_sim *s : b->sims) b->walls = b->walls || s->wd.on;
+    b->walls = walls;
     return LBM_OK;
 }
 
@@ -781,7 +839,6 @@ lbm_status lbm_batch_create(int32_t max_sims, void *workspace, size_t workspace_
     b->generation = 0;
     b->threads = BATCH_DEFAULT_THREADS;
     b->blocks = 0;
-    b->upload_pending = false;
     b->walls = false;
     *out = b;
     return ok();
@@ -832,13 +889,7 @@ lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t threads, int64_t blocks)
     return ok();
 }
 
-void lbm_batch_destroy(lbm_batch *b)
-{
-    if (!b) return;
-    // the last tile-table upload reads the host staging copy owned here
-    if (b->upload_pending) (void)hipStreamSynchronize(b->stream);
-    delete b;
-}
+void lbm_batch_destroy(lbm_batch *b) { delete b; }
 
 }  // extern "C"
 
@@ -846,23 +897,11 @@ void lbm_batch_destroy(lbm_batch *b)
 // batch step without a workspace: the tile table in a fixed device array
 // ---------------------------------------------------------------------------
 namespace {
-// members per table-fill launch: their descriptors travel as kernel arguments
-constexpr int NOALLOC_CHUNK = 16;
 constexpr size_t NOALLOC_BEGIN_BYTES = (size_t(LBM_NOALLOC_MAX_SIMS + 1) * 8 + ALIGN - 1) /
                                        ALIGN * ALIGN;
 constexpr size_t NOALLOC_SCRATCH_BYTES =
     NOALLOC_BEGIN_BYTES + size_t(LBM_NOALLOC_MAX_SIMS) * sizeof(TileSim);
 constexpr int NOALLOC_MAX_DEVICES = 64;
-
-// Members first .. first + n - 1 of a tile table; `last` also sets the end of
-// the list, begin[first + n] = end.
-struct TableChunk {
-    int32_t first, n, last;
-    int64_t end;
-    int64_t begin[NOALLOC_CHUNK];
-    TileSim sims[NOALLOC_CHUNK];
-};
-static_assert(sizeof(TableChunk) <= 4000, "kernel arguments are limited to 4 KiB");
 
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
@@ -873,18 +912,6 @@ void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
 // member.  Host code reaches it only through the address hipGetSymbolAddress
 // returns for the current device.
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
-
-__global__ void __launch_bounds__(64) table_fill_kernel(TableChunk c, unsigned char *base)
-{
-    int64_t *begin = reinterpret_cast<int64_t *>(base);
-    TileSim *tab = reinterpret_cast<TileSim *>(base + NOALLOC_BEGIN_BYTES);
-    const int t = int(threadIdx.x);
-    if (t < c.n) {
-        begin[c.first + t] = c.begin[t];
-        tab[c.first + t] = c.sims[t];
-    }
-    if (t == 0 && c.last) begin[c.first + c.n] = c.end;
-}
 
 namespace {
 // Device address of `scratch` on the current device, resolved once per device.
@@ -919,17 +946,8 @@ lbm_status lbm_batch_step_noalloc(lbm_sim *const *sims, int32_t count, int64_t n
                     "count must be in [1, %d]: the fixed tile table holds %d members (got %d)",
                     LBM_NOALLOC_MAX_SIMS, LBM_NOALLOC_MAX_SIMS, count);
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    for (int32_t k = 0; k < count; ++k) {
-        const lbm_sim *s = sims[k];
-        if (!s) return fail(LBM_EINVAL, "sims[%d] is NULL", k);
-        for (int32_t j = 0; j < k; ++j)
-            if (sims[j] == s) return fail(LBM_EINVAL, "sims[%d] repeats sims[%d]", k, j);
-        const lbm_sim *s0 = sims[0];
-        if (s->p.lattice != s0->p.lattice || s->p.storage != s0->p.storage || s->eq != s0->eq ||
-            s->p.force_order != s0->p.force_order)
-            return fail(LBM_EINVAL,
-                        "batch members must share lattice, storage, eq_order and force_order");
-    }
+    lbm_status st = check_members(sims, count);
+    if (st != LBM_OK) return st;
     if (nsteps == 0) return ok();
     unsigned char *base = nullptr;
     hipError_t e = scratch_address(&base);
@@ -940,30 +958,13 @@ lbm_status lbm_batch_step_noalloc(lbm_sim *const *sims, int32_t count, int64_t n
         e = wall_densities(sims[k], stream);
         if (e != hipSuccess) return dev_fail(e, "wall density kernel launch");
     }
-    // the tile table, NOALLOC_CHUNK members per fill launch
+    int64_t *begin = reinterpret_cast<int64_t *>(base);
+    TileSim *table = reinterpret_cast<TileSim *>(base + NOALLOC_BEGIN_BYTES);
     int64_t tiles = 0;
     bool walls = false;
-    for (int32_t first = 0; first < count; first += NOALLOC_CHUNK) {
-        TableChunk c;
-        std::memset(&c, 0, sizeof c);
-        c.first = first;
-        c.n = std::min<int32_t>(NOALLOC_CHUNK, count - first);
-        for (int32_t k = 0; k < c.n; ++k) {
-            const lbm_sim *s = sims[first + k];
-            fill_tile_sim(c.sims[k], s, tiles);
-            c.begin[k] = tiles;
-            tiles += int64_t(c.sims[k].chunks_x) * s->p.ny * s->p.nz;
-            walls = walls || s->wd.on;
-        }
-        c.last = first + c.n == count;
-        c.end = tiles;
-        hipLaunchKernelGGL(table_fill_kernel, dim3(1), dim3(64), 0, stream, c, base);
-        e = hipGetLastError();
-        if (e != hipSuccess) return dev_fail(e, "tile table fill launch");
-    }
+    e = upload_table(sims, count, begin, table, stream, tiles, walls);
+    if (e != hipSuccess) return dev_fail(e, "tile table fill launch");
     const lbm_sim *s0 = sims[0];
-    const int64_t *begin = reinterpret_cast<const int64_t *>(base);
-    const TileSim *table = reinterpret_cast<const TileSim *>(base + NOALLOC_BEGIN_BYTES);
     int64_t done = 0;
     for (; done < nsteps; ++done) {
         const BatchLaunch bl{begin,  table, int(count), tiles, int(done & 1), BATCH_DEFAULT_THREADS,

@@ -716,27 +716,45 @@ __device__ __forceinline__ double block_sum_256(double v, double *lds)
     return (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
-template <int LAT>
+// Stage 1: block b sums the cells of a fixed run of grid rows, every lane
+// holding one FP64 accumulator per population: the block's cells are taken
+// in order, lane t the t-th of every 256, all Q planes of a cell loaded
+// together; then each accumulator is reduced across the block in a fixed tree.
+template <int LAT, class S>
 __global__ void __launch_bounds__(256)
-    totals_stage1(const void *__restrict__ A, int storage, double *__restrict__ partials,
-                  GridDims gd)
+    totals_stage1(const S *__restrict__ A, double *__restrict__ partials, GridDims gd,
+                  DivU32 by_nx)
 {
     using L = Lattice<LAT>;
-    __shared__ double lds[4];
-    // block b sums a fixed run of grid rows (the padding of each row is skipped)
+    __shared__ double lds[4][L::Q];
     const int64_t rows = int64_t(gd.ny) * gd.nz;
     const int64_t chunk = (rows + TOTALS_BLOCKS - 1) / TOTALS_BLOCKS;
     const int64_t lo = int64_t(blockIdx.x) * chunk;
     const int64_t hi = (lo + chunk < rows) ? lo + chunk : rows;
+    double acc[L::Q];
+    static_for<0, L::Q>([&](auto I) { acc[decltype(I)::value] = 0.0; });
+    // cells of the block, < 2^32: a block holds at most ceil(rows / 512) rows
+    const uint32_t ncell = hi > lo ? uint32_t((hi - lo) * gd.nx) : 0u;
+    for (uint32_t k = threadIdx.x; k < ncell; k += 256) {
+        const uint32_t dr = divu(by_nx, k);
+        const int64_t idx = (lo + dr) * gd.px + (k - dr * uint32_t(gd.nx));
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            acc[i] += Codec<L, S>::template load<i, double>(A[int64_t(i) * gd.P + idx]);
+        });
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        double v = 0.0;
-        for (int64_t r = lo; r < hi; ++r)
-            for (int x = threadIdx.x; x < gd.nx; x += 256)
-                v += load_any<L, i>(A, storage, int64_t(i) * gd.P + r * gd.px + x);
-        v = block_sum_256(v, lds);
-        if (threadIdx.x == 0) partials[int64_t(blockIdx.x) * L::Q + i] = v;
+        double v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) lds[wid][i] = v;
     });
+    __syncthreads();
+    if (threadIdx.x < L::Q) {
+        const int i = threadIdx.x;
+        partials[int64_t(blockIdx.x) * L::Q + i] = (lds[0][i] + lds[1][i]) + (lds[2][i] + lds[3][i]);
+    }
 }
 
 template <int LAT>

@@ -209,8 +209,16 @@ template <int LAT>
 hipError_t launch_totals_l(int storage, const void *A, double *partials, double *out_dev,
                            const GridDims &gd, const StepCoef &co, hipStream_t stream)
 {
-    hipLaunchKernelGGL((totals_stage1<LAT>), dim3(TOTALS_BLOCKS), dim3(256), 0, stream, A,
-                       storage, partials, gd);
+    const DivU32 by_nx = make_divu32(uint32_t(gd.nx));
+    if (storage == 0)
+        hipLaunchKernelGGL((totals_stage1<LAT, double>), dim3(TOTALS_BLOCKS), dim3(256), 0, stream,
+                           static_cast<const double *>(A), partials, gd, by_nx);
+    else if (storage == 1)
+        hipLaunchKernelGGL((totals_stage1<LAT, float>), dim3(TOTALS_BLOCKS), dim3(256), 0, stream,
+                           static_cast<const float *>(A), partials, gd, by_nx);
+    else
+        hipLaunchKernelGGL((totals_stage1<LAT, __half>), dim3(TOTALS_BLOCKS), dim3(256), 0, stream,
+                           static_cast<const __half *>(A), partials, gd, by_nx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((totals_stage2<LAT>), dim3(1), dim3(256), 0, stream, partials, out_dev,

@@ -200,6 +200,18 @@ class Sim:
         check(load().lbm_totals(self.handle, out))
         return np.array(out[:])
 
+    def totals_device(self, out=None):
+        """The totals of totals(), as D+2 float64 on the device, enqueued on the
+        handle's stream without waiting (no finiteness check); ready on the
+        caller's current stream."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.D + 2, dtype=torch.float64, device=self.device)
+        cur = self._before()
+        check(load().lbm_totals_device(self.handle, ctypes.c_void_p(out.data_ptr())))
+        self._after(cur, out)
+        return out
+
     def population_bytes(self) -> int:
         return int(load().lbm_population_bytes(self.handle))
 

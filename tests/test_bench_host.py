@@ -12,12 +12,16 @@ import bench
 def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2302_04741_amd" / "csrc"
     csrc.mkdir(parents=True)
-    src = csrc / "k.hip"
+    src = csrc / "lbm_kernels.h"
     src.write_text("// a kernel\nint f(int x) { return x + 1; }  /* one */\n")
+    host = csrc / "lbm_api.hip"
+    host.write_text("int g(void) { return 0; }\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.kernel_source_hash()
     src.write_text("// the same kernel, reworded\n\nint f(int x) { return x + 1; }\n"
                    "/* a block\n   comment */\n")
+    assert bench.kernel_source_hash() == h0
+    host.write_text("int g(void) { return 1; }\n")  # host code: not the measured kernel
     assert bench.kernel_source_hash() == h0
     src.write_text("int f(int x) { return x + 2; }\n")
     assert bench.kernel_source_hash() != h0

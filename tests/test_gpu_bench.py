@@ -16,7 +16,7 @@ def test_bench_line_fields():
     buf = io.StringIO()
     with contextlib.redirect_stdout(buf):
         rc = bench.main(["--n", "64", "--steps", "5", "--warmup", "2", "--repeats", "2",
-                         "--cpu-steps", "0"])
+                         "--cpu-steps", "0", "--no-serve"])
     assert rc == 0
     lines = [ln for ln in buf.getvalue().splitlines() if ln.startswith("{")]
     assert len(lines) == 1
@@ -35,6 +35,24 @@ def test_bench_line_fields():
     p = d["pattern_ceiling"]
     assert p["achieved"] > 0 and set(p["by_block"]) == {"256", "512", "1024"}
     assert d["repeats"]["count"] == 2
+
+
+def test_bench_line_serving_fields():
+    """The default line carries the serving figures (here on a short stream)."""
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        rc = bench.main(["--n", "64", "--steps", "3", "--warmup", "1", "--repeats", "0",
+                         "--cpu-steps", "0", "--serve-count", "12", "--req-steps", "100",
+                         "--rate", "100"])
+    assert rc == 0
+    lines = [ln for ln in buf.getvalue().splitlines() if ln.startswith("{")]
+    d = json.loads(lines[-1])
+    sv = d["serving"]
+    assert sv["requests"] == 12 and sv["failed"] == 0 and sv["queued_failed"] == 0
+    assert 0 < sv["p50_latency_s"] <= sv["p99_latency_s"]
+    for k in ("live_aggregate_mlups", "queued_aggregate_mlups", "sequential_aggregate_mlups"):
+        assert sv[k] > 0, k
+    assert sv["workload"].startswith("12 D2Q37 requests")
 
 
 def test_bench_line_d2q37():

@@ -15,6 +15,16 @@ Per configuration:
     in y (the flow varies in y only); pointwise the CE estimate also carries
     O(gradient) corrections.
   * FP32 resolves that difference: its mode within 3% of FP64's.
+  * The scheme without a3_F (force order 2) run as its own 5000-step
+    simulation from the same initial state, in FP64 and FP32: FP32 against
+    FP64 within the same bars as the full scheme.  The full-size difference of
+    the two schemes after 5000 steps (rho, u, theta and q, FP64) is printed.
+    Its temperature part (2.5e-7 to 1.6e-6 of theta at dtheta 0.02, 1.2e-5 to
+    1.4e-5 at dtheta 0.1) is resolved by FP32 only where it exceeds FP32's own
+    coherent theta drift over the run (7e-6 to 1.4e-4): at dtheta 0.1 the FP32
+    difference of the two schemes on its dominant y-mode is within 15% of
+    FP64's (measured 0.9-7.3%); at dtheta 0.02 it is not (16-95%), which the
+    test records as the scheme difference staying below 3x the FP32 error.
 
 Measured values are printed; the bars are about 3x above the largest of them.
 """
@@ -66,6 +76,24 @@ def ymode(f, n):
     return np.stack(out, -1)
 
 
+def run_plain(sim_mod, tau, dth, ma, storage, stream, force_order):
+    """A 5000-step run of one scheme from the initial state: MLUPS, moments, q."""
+    wl = workloads.thermal_shear_2d(n=1024, tau_hat=tau, dtheta=dth, mach=ma, steps=STEPS,
+                                    force_order=force_order)
+    s = sim_mod.from_workload(wl, storage=storage, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(STEPS)
+    e1.record(stream)
+    e1.synchronize()
+    mlups = wl.ncell * STEPS / e0.elapsed_time(e1) / 1e3
+    m = gpu_moments(s)
+    q = to_host(s.heat_flux())
+    s.close()
+    return mlups, m, q
+
+
 def run(sim_mod, tau, dth, ma, storage, stream):
     wl = workloads.thermal_shear_2d(n=1024, tau_hat=tau, dtheta=dth, mach=ma, steps=STEPS)
     s = sim_mod.from_workload(wl, storage=storage, stream=stream)
@@ -112,3 +140,32 @@ def test_thermal_shear_1024_sweep(sim_mod, tau, dth, ma):
     assert eq <= TOL_Q32
     assert ce <= TOL_CE
     assert p32 <= TOL_DQ32
+
+    # the scheme without a3_F as its own 5000-step run
+    r64_2, m64_2, q64_2 = run_plain(sim_mod, tau, dth, ma, "f64", stream, 2)
+    r32_2, m32_2, q32_2 = run_plain(sim_mod, tau, dth, ma, "f32", stream, 2)
+    e2 = rel_err(m32_2, m64_2)
+    eq2 = np.abs(q32_2 - q64_2).max() / np.abs(q64_2).max()
+    # the two schemes after 5000 steps (FP64), relative like the parity metric
+    d_sch = rel_err(m64_2, m64)
+    dq_sch = np.abs(q64_2 - q64).max() / np.abs(q64).max()
+    dth64 = m64_2[2] - m64[2]
+    dth32 = m32_2[2] - m32[2]
+    a64, a32 = ymode(dth64[None], 1024)[0], ymode(dth32[None], 1024)[0]
+    j = np.argmax(np.abs(a64))
+    p_th = abs(a32[j] / a64[j] - 1.0)
+    err32_th = max(np.abs(m32_2[2] - m64_2[2]).max(), np.abs(m32[2] - m64[2]).max())
+    print("  order 2, 5000 steps | MLUPS f64 %.0f f32 %.0f | FP32 vs FP64: rho %.1e u %.1e "
+          "theta %.1e q %.1e | order 2 vs 4 (FP64): rho %.1e u %.1e theta %.1e q %.1e, "
+          "max|dtheta| %.2e | FP32 dtheta mode %.1e, FP32 theta error %.1e"
+          % (r64_2, r32_2, *e2, eq2, *d_sch, dq_sch, np.abs(dth64).max(), p_th, err32_th),
+          flush=True)
+    assert all(x <= t for x, t in zip(e2, TOL32)), e2
+    assert eq2 <= TOL_Q32
+    assert np.abs(dth64).max() > 0.0
+    if dth >= 0.1:
+        assert p_th <= 0.15
+    else:
+        # below FP32's resolution over 5000 steps (the 50-step heat-flux
+        # branches above resolve the correction itself)
+        assert np.abs(dth64).max() <= 3.0 * err32_th
