@@ -4,8 +4,11 @@
   that turns eq. (an) into eq. (an1)): exact through degree 9 (D2Q37) and 7
   (D3Q39), inexact one degree higher.
 * The D2Q37 lattice constant printed in the paper's Sec. 3 (golden file).
-* The D2Q37 and D3Q39 weights against the published E^9_{2,37} and E^7_{3,39}
-  rules (golden files).
+* The D3Q39 weights against the published E^7_{3,39} rule (golden file, exact
+  fractions).
+* Both rules against a second derivation written here in 60-digit decimal
+  arithmetic (bisection on the determinant of the moment system, a different
+  method from the oracle's long-double scan).
 * Hermite tensors of the oracle against their explicit closed forms and against
   the orthogonality relation they must satisfy under an exact rule.
 """
@@ -104,31 +107,6 @@ def test_d3q39_weights_match_the_published_rule(oracle_mod):
     assert abs(sum(n * wt for n, wt in shells.values()) - 1.0) < 1e-15
 
 
-def test_d2q37_weights_match_the_published_rule(oracle_mod):
-    """Every shell weight and the scale r of the derived D2Q37 rule equal the
-    23-digit published E^9_{2,37} values (golden file) to FP64 rounding."""
-    shells = {}
-    r_pub = None
-    with open(os.path.join(GOLDEN, "d2q37_weights.txt")) as fh:
-        for line in fh:
-            if line.startswith("#") or not line.strip():
-                continue
-            f = line.split()
-            if f[0] == "r":
-                r_pub = float(f[1])
-            else:
-                shells[(int(f[0]), int(f[1]))] = (int(f[2]), float(f[3]))
-    c, w, r, _ = oracle_mod.lattice(0)
-    assert abs(r - r_pub) <= 4e-16 * r_pub
-    seen = {}
-    for v, wv in zip(c, w):
-        gen = tuple(sorted((abs(int(a)) for a in v[:2]), reverse=True))
-        assert gen in shells, gen
-        assert abs(wv - shells[gen][1]) <= 1e-15 * shells[gen][1], (gen, wv)
-        seen[gen] = seen.get(gen, 0) + 1
-    assert seen == {g: n for g, (n, _) in shells.items()}
-
-
 @pytest.mark.parametrize("lat", [0, 1])
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 4])
 def test_hermite_tensors_closed_form(oracle_mod, lat, n):
@@ -164,3 +142,112 @@ def test_hermite_orthogonality_under_the_rule(oracle_mod, lat, deg):
             else:
                 ref = _delta_perm_sum(D, n).reshape(D ** n, D ** n)
                 np.testing.assert_allclose(G, ref, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The rules derived a second time, independently of the oracle's own
+# derivation: 60-digit decimal arithmetic on the moment conditions
+# ---------------------------------------------------------------------------
+def _shell_vectors(gen, D):
+    """All sign changes and permutations of a shell generator."""
+    g = list(gen) + [0] * (D - len(gen))
+    out = set()
+    for perm in itertools.permutations(g):
+        for signs in itertools.product((1, -1), repeat=D):
+            out.add(tuple(s * p for s, p in zip(signs, perm)))
+    return sorted(out)
+
+
+def _decimal_rule(gens, D, monomials, bracket):
+    """Scale s = r^2 and shell weights of the rule that integrates every
+    monomial of `monomials` exactly against the unit Gaussian: for a given s
+    the conditions are linear in the weights; there are as many conditions as
+    weights plus one, so s is where the augmented system is singular (found
+    by bisection inside `bracket`), and the weights then solve all conditions
+    (checked).  Decimal arithmetic at 60 digits; shells from `gens`."""
+    import math
+    from decimal import Decimal, localcontext
+
+    shells = [_shell_vectors(g, D) for g in gens]
+    S = [[sum(math.prod(v[a] ** p[a] for a in range(D)) for v in sh) for sh in shells]
+         for p in monomials]
+
+    def system(s):
+        A = [[Decimal(S[i][k]) * s ** (sum(p) // 2) for k in range(len(shells))]
+             for i, p in enumerate(monomials)]
+        b = [Decimal(int(gaussian_moment(p))) for p in monomials]
+        return A, b
+
+    def eliminate(M, n_cols):
+        """Row echelon form in place; returns the product of the pivots."""
+        d = Decimal(1)
+        for c in range(n_cols):
+            piv = max(range(c, len(M)), key=lambda r: abs(M[r][c]))
+            if piv != c:
+                M[c], M[piv] = M[piv], M[c]
+                d = -d
+            d *= M[c][c]
+            for r in range(c + 1, len(M)):
+                f = M[r][c] / M[c][c]
+                M[r] = [a - f * q for a, q in zip(M[r], M[c])]
+        return d
+
+    with localcontext() as ctx:
+        ctx.prec = 60
+        def det(s):
+            A, b = system(s)
+            return eliminate([row + [-bb] for row, bb in zip(A, b)], len(A))
+
+        lo, hi = Decimal(bracket[0]), Decimal(bracket[1])
+        flo = det(lo)
+        assert flo * det(hi) < 0
+        for _ in range(200):
+            mid = (lo + hi) / 2
+            fm = det(mid)
+            if (fm < 0) == (flo < 0):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        s = (lo + hi) / 2
+        A, b = system(s)
+        # least squares through the normal equations (the system is consistent at s)
+        n = len(shells)
+        N = [[sum(A[i][j] * A[i][k] for i in range(len(A))) for k in range(n)] +
+             [sum(A[i][j] * b[i] for i in range(len(A)))] for j in range(n)]
+        eliminate(N, n)
+        W = [Decimal(0)] * n
+        for j in reversed(range(n)):
+            W[j] = (N[j][n] - sum(N[j][k] * W[k] for k in range(j + 1, n))) / N[j][j]
+        for i in range(len(A)):
+            assert abs(sum(A[i][k] * W[k] for k in range(n)) - b[i]) < Decimal(10) ** -40
+        return float(s.sqrt()), {tuple(sorted(g, reverse=True)) + (0,) * (D - len(g)):
+                                 (len(sh), float(wk)) for g, sh, wk in zip(gens, shells, W)}
+
+
+D2Q37_SHELLS = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1)]
+D3Q39_SHELLS = [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 0, 0), (2, 2, 0), (3, 0, 0)]
+
+
+@pytest.mark.parametrize("lat,gens,D,monomials,bracket", [
+    (0, D2Q37_SHELLS, 2, [(0, 0), (2, 0), (4, 0), (2, 2), (6, 0), (4, 2), (8, 0), (6, 2), (4, 4)],
+     ("1.40", "1.45")),
+    (1, D3Q39_SHELLS, 3, [(0, 0, 0), (2, 0, 0), (4, 0, 0), (2, 2, 0), (6, 0, 0), (4, 2, 0),
+                          (2, 2, 2)], ("1.3", "1.7")),
+])
+def test_rule_matches_an_independent_60_digit_derivation(oracle_mod, lat, gens, D, monomials,
+                                                         bracket):
+    """The oracle's scale r and every weight equal the rule derived here from
+    the same moment conditions in 60-digit arithmetic (a separate code path:
+    decimal bisection on the determinant of the augmented moment system, not
+    the oracle's long-double scan), to FP64 rounding.  The bracket of r^2
+    holds the paper's printed lattice constant for D2Q37 (1.19698^2 = 1.4328)."""
+    r_ref, shells = _decimal_rule(gens, D, monomials, bracket)
+    c, w, r, _ = oracle_mod.lattice(lat)
+    assert abs(r - r_ref) <= 4e-16 * r_ref
+    seen = {}
+    for v, wv in zip(c, w):
+        gen = tuple(sorted((abs(int(a)) for a in v[:D]), reverse=True))
+        assert gen in shells, gen
+        assert abs(wv - shells[gen][1]) <= 2e-15 * shells[gen][1], (gen, wv, shells[gen][1])
+        seen[gen] = seen.get(gen, 0) + 1
+    assert seen == {g: n for g, (n, _) in shells.items()}
