@@ -66,7 +66,12 @@ typedef enum { LBM_D2Q37 = 0, LBM_D3Q39 = 1 } lbm_lattice;
 /* Population storage.  Arithmetic runs in FP64 for LBM_F64 and FP32 for
  * LBM_F32 and LBM_F16DEV.  Every storage type holds h_i = f~_i - w_i rho0
  * (see lbm_params.rho0); LBM_F16DEV stores h_i scaled by 2^k_i, k_i =
- * round(-log2 w_i), as IEEE half, so that deviations stay normal numbers. */
+ * round(-log2 w_i), as IEEE half, so that deviations stay normal numbers.
+ * The step stores LBM_F16DEV values with stochastic rounding (up or down with
+ * probabilities that make the rounding error zero-mean), its random bits a
+ * hash of (cell, population, step number): deterministic, and independent of
+ * launch shape, batching and the other members; the initial state rounds to
+ * nearest. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
 
 /* Truncation of the force expansion eq. (F).  The paper's N = 0, 1, 2 are
@@ -105,7 +110,7 @@ typedef struct {
 /* Bytes of device workspace a handle needs for these parameters (256-byte
  * aligned sub-buffers included): two arrays of the Q populations f~_i of
  * eq. (lbm), in planes whose rows are padded to a multiple of 64 values, the
- * force table, and the reduction scratch of lbm_totals (with LBM_FLAG_WALLS
+ * force table, the reduction scratch of lbm_totals and a step counter (with LBM_FLAG_WALLS
  * also the plates' row sums and emission tables).  Returns 0 if the
  * parameters are invalid. */
 LBM_API size_t lbm_workspace_bytes(const lbm_params *p);
@@ -199,7 +204,9 @@ LBM_API lbm_status lbm_pattern_pass(lbm_sim *s, int64_t repeats);
  * storage type, value i*N + cell (the padding
  * of the internal rows is dropped), post-collision "pull" layout.  get copies
  * out, set copies in (device buffers, async on the handle's stream).
- * Restoring a state together with lbm_set_step_count resumes bitwise. */
+ * Restoring a state together with lbm_set_step_count resumes bitwise (with
+ * F16 storage the step number keys the stochastic rounding: set_step_count
+ * also sets the device counter, asynchronously on the handle's stream). */
 LBM_API size_t lbm_population_bytes(const lbm_sim *s);
 LBM_API lbm_status lbm_get_populations(lbm_sim *s, void *dst);
 LBM_API lbm_status lbm_set_populations(lbm_sim *s, const void *src);

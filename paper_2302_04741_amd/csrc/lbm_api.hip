@@ -37,6 +37,7 @@ struct lbm_sim {
     size_t gtab_bytes;
     double *partials;
     double *totals_dev;
+    uint32_t *ctr;  // device step counter pair of the F16 stochastic rounding (in the totals slot)
     int64_t step;
     int block;
     int64_t gen;  // bumped when launch arguments change (force, block, stream, viscosity,
@@ -130,6 +131,20 @@ Layout layout_of(const lbm_params *p)
     return L;
 }
 
+// Device step counter of a handle: the step sets ctr[cur] = n, read by the
+// next step (F16 stochastic rounding keys).
+__global__ void __launch_bounds__(64) set_step_number_kernel(uint32_t *ctr, int cur, uint32_t n)
+{
+    if (threadIdx.x == 0) ctr[cur] = n;
+}
+
+hipError_t set_step_number(const lbm_sim *s)
+{
+    hipLaunchKernelGGL(set_step_number_kernel, dim3(1), dim3(64), 0, s->stream, s->ctr, s->cur,
+                       uint32_t(s->step));
+    return hipGetLastError();
+}
+
 lbm_status check_params(const lbm_params *p)
 {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
@@ -171,7 +186,7 @@ lbm_status check_params(const lbm_params *p)
 // partial sums of that buffer).
 LaunchCfg cfg(const lbm_sim *s, int cur)
 {
-    LaunchCfg c{s->block, s->stream, s->wd};
+    LaunchCfg c{s->block, s->stream, s->wd, s->ctr, cur};
     c.walls.par = cur;
     return c;
 }
@@ -289,6 +304,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->fd.tab = s->gtab;
     s->partials = reinterpret_cast<double *>(s->ws + L.off_part);
     s->totals_dev = reinterpret_cast<double *>(s->ws + L.off_tot);
+    s->ctr = reinterpret_cast<uint32_t *>(s->ws + L.off_tot + 8 * sizeof(double));
     s->wd = WallDesc{0, 0, nullptr, nullptr};
     s->wall_part = nullptr;
     s->wall_e = nullptr;
@@ -303,6 +319,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     s->resident_max = RESIDENT_DEFAULT_MAX_CELLS;
     hipError_t e = launch_init(p->lattice, p->storage, s->eq, p->force_order, rho, u, theta,
                                s->pop[0], s->gd, s->fd, s->co, cfg(s));
+    if (e == hipSuccess) e = set_step_number(s);
     if (e != hipSuccess) {
         delete s;
         return dev_fail(e, "init kernel launch");
@@ -507,6 +524,8 @@ lbm_status lbm_set_step_count(lbm_sim *s, int64_t n)
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_EINVAL, "step count must be >= 0");
     s->step = n;
+    hipError_t e = set_step_number(s);
+    if (e != hipSuccess) return dev_fail(e, "step counter kernel launch");
     return ok();
 }
 
@@ -659,6 +678,7 @@ void fill_tile_sim(TileSim &t, const lbm_sim *s, int64_t first_tile)
 {
     t.pop[0] = s->pop[0];
     t.pop[1] = s->pop[1];
+    t.ctr = s->ctr;
     t.cur = s->cur;
     t.chunks_x = int32_t((s->p.nx + 63) / 64);
     t.tile_begin = first_tile;

@@ -226,6 +226,7 @@ __host__ __device__ inline int64_t wall_part_index(int par, int side, int k, int
 // (z, y) order.
 struct TileSim {
     const void *pop[2];  // the two population buffers
+    uint32_t *ctr;       // step counter pair (F16 stochastic rounding keys), see LaunchCfg
     int32_t cur;         // buffer holding the state when the table was built
     int32_t chunks_x;    // tiles per grid row, ceil(nx / 64)
     int64_t tile_begin;  // first tile of this simulation in the list
@@ -571,6 +572,8 @@ struct LaunchCfg {
     int block;  // threads along x per block
     hipStream_t stream;
     WallDesc walls;  // off unless the handle has plates
+    uint32_t *ctr;   // the handle's step counter pair (keys of the F16 stochastic rounding)
+    int cur;         // buffer holding the state read: the step reads ctr[cur], writes ctr[cur ^ 1]
 };
 
 // Generic entry points (lbm_dispatch.hip), switching on lattice and storage.

@@ -30,22 +30,68 @@ template <> struct ArithOf<double> { using type = double; };
 template <> struct ArithOf<float> { using type = float; };
 template <> struct ArithOf<__half> { using type = float; };
 
+// Random bits of the F16 stochastic rounding.  One 32-bit key per (cell,
+// step): the cell index and the step number combined linearly, then the
+// 32-bit finalizer of MurmurHash3 (Appleby) to spread every input bit over
+// the word.  The cell's stores then walk a 32-bit linear congruential
+// sequence from that key (Knuth's multiplier 6364136223846793005 reduced to
+// its low word, odd increment), each store taking the top 13 bits of the
+// current word: a uniform value below 2^13.  Nothing depends on the launch
+// shape, the batch or the other members.
+__device__ __forceinline__ uint32_t sr_key(uint32_t cell, uint32_t step)
+{
+    uint32_t h = cell * 0x9E3779B1u + step * 0x85EBCA77u;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+struct SrStream {
+    uint32_t x;
+    __device__ __forceinline__ uint32_t next13()
+    {
+        const uint32_t r = x >> 19;
+        x = x * 0x4C957F2Du + 0x2545F491u;
+        return r;
+    }
+};
+
+// float -> binary16 with stochastic rounding: a value between two
+// neighbouring halves a < v < b rounds to b with probability (v - a)/(b - a),
+// so the rounding error has zero mean whatever v is.  On the FP32 bit
+// pattern (sign and magnitude): add a uniform 13-bit integer below the
+// 13 bits that binary16 drops, clear them; the result is a half exactly
+// (converted without further rounding) for |v| >= 2^-14.  Below that, in the
+// half subnormal range, the conversion rounds the dithered value to nearest
+// (an error below 2^-25).
+__device__ __forceinline__ __half half_sr(float v, uint32_t r13)
+{
+    const uint32_t b = (__builtin_bit_cast(uint32_t, v) + r13) & 0xFFFFE000u;
+    return __float2half_rn(__builtin_bit_cast(float, b));
+}
+
 // load/store convert between a stored value and the deviation h_i it stands
 // for; load_scaled/store_scaled keep the factor scale<I>() the stored value
 // carries (the fused step works on scaled values: see raw_sums, combo_pairs).
 template <class L, class S> struct Codec {
+    static constexpr bool STOCHASTIC = false;
     template <int I> static constexpr double scale() { return 1.0; }
     template <int I, class T> __device__ static __forceinline__ T load(S v) { return T(v); }
     template <int I, class T> __device__ static __forceinline__ S store(T h) { return S(h); }
     template <int I, class T> __device__ static __forceinline__ T load_scaled(S v) { return T(v); }
-    template <int I, class T> __device__ static __forceinline__ S store_scaled(T h)
+    template <int I, class T> __device__ static __forceinline__ S store_scaled(T h, SrStream &)
     {
         return S(h);
     }
 };
 
-// F16 deviations: stored value h_i 2^k_i, k_i = round(-log2 w_i).
+// F16 deviations: stored value h_i 2^k_i, k_i = round(-log2 w_i).  The step
+// stores with stochastic rounding (store_scaled); the initial state and the
+// kernels off the step path round to nearest (store).
 template <class L> struct Codec<L, __half> {
+    static constexpr bool STOCHASTIC = true;
     template <int I> static constexpr double scale()
     {
         double s = 1.0;
@@ -66,9 +112,11 @@ template <class L> struct Codec<L, __half> {
     {
         return T(__half2float(v));
     }
-    template <int I, class T> __device__ static __forceinline__ __half store_scaled(T h)
+    // stochastic rounding (half_sr), the next 13 random bits of the cell's stream
+    template <int I, class T> __device__ static __forceinline__ __half store_scaled(T h,
+                                                                                   SrStream &rng)
     {
-        return __float2half_rn(float(h));
+        return half_sr(float(h), rng.next13());
     }
 };
 
@@ -158,11 +206,13 @@ template <int LAT, class S> inline int step_default_threads(int64_t waves)
 
 // The fused update of one cell (x, y, z): gather, moments, equilibrium, stress,
 // force, relaxation, store.  y and z must be uniform over the wavefront.
+// `step` is the step number (the state read is after `step` steps): with F16
+// storage it keys the stochastic rounding of every value stored.
 template <int LAT, class S, int EQ, int FO, bool WALLS = false, bool LANE_ROWS = false>
 __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict__ B,
                                           const GridDims &gd, const ForceDesc &fd,
                                           const StepCoef &co, int x, int y, int z,
-                                          const WallDesc *wd = nullptr)
+                                          uint32_t step, const WallDesc *wd = nullptr)
 {
     using L = Lattice<LAT>;
     using T = typename ArithOf<S>::type;
@@ -177,6 +227,7 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // storage is reduced-precision); the sums and the pair terms take the
     // scale through their constants, so no value is rescaled on the way.
     using C = Codec<L, S>;
+    SrStream rng{C::STOCHASTIC ? sr_key(uint32_t(cell), step) : 0u};
     T h[L::Q];
     gather<L, S, T, WALLS, LANE_ROWS>(A, gd, x, y, z, h, wd, co.rho0);
     T g[3];
@@ -216,12 +267,12 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip)) * C::template scale<ip>();
         const T dp = fma_t(T(w), drho, -h[ip]);
-        const S sp = C::template store_scaled<ip, T>(h[ip] + fma_t(om, dp, ev + od));
+        const S sp = C::template store_scaled<ip, T>(h[ip] + fma_t(om, dp, ev + od), rng);
         BufIO<S>::store(sp, plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
         account(IP, sp);
         if constexpr (im >= 0) {
             const T dm = fma_t(T(w), drho, -h[im]);
-            const S sm = C::template store_scaled<im, T>(h[im] + fma_t(om, dm, ev - od));
+            const S sm = C::template store_scaled<im, T>(h[im] + fma_t(om, dm, ev - od), rng);
             BufIO<S>::store(sm, plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
             account(IM, sm);
         }
@@ -232,6 +283,25 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
         const int y1 = gd.ny > 3 ? gd.ny - 3 : 0;  // first row of the top plate's sums
         if (y < 3) wd->part[wall_part_index(wd->par ^ 1, 0, y, ncol, col)] = ps[0];
         if (y >= y1) wd->part[wall_part_index(wd->par ^ 1, 1, y - y1, ncol, col)] = ps[1];
+    }
+}
+
+// Step counter of a handle (F16 storage only): a pair of words; a step that
+// reads buffer `cur` reads the step number from ctr[cur] and one lane writes
+// the next number to ctr[cur ^ 1], which the next step reads.  The launches
+// of a step loop, eager or captured in a graph, so carry the count without
+// the host.
+template <class S> __device__ __forceinline__ uint32_t step_number(const uint32_t *ctr, int cur)
+{
+    if constexpr (Codec<Lattice<0>, S>::STOCHASTIC) return __builtin_amdgcn_readfirstlane(ctr[cur]);
+    else return 0u;
+}
+template <class S>
+__device__ __forceinline__ void advance_step_number(uint32_t *ctr, int cur, uint32_t step,
+                                                    bool writer)
+{
+    if constexpr (Codec<Lattice<0>, S>::STOCHASTIC) {
+        if (writer) ctr[cur ^ 1] = step + 1u;
     }
 }
 
@@ -256,13 +326,16 @@ template <int LAT, class S, int EQ, int FO>
 __global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__restrict__ A,
                                                                      S *__restrict__ B,
                                                                      GridDims gd, ForceDesc fd,
-                                                                     StepCoef co)
+                                                                     StepCoef co, uint32_t *ctr,
+                                                                     int cur)
 {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
                                                          (threadIdx.x >> 6));
+    const uint32_t step = step_number<S>(ctr, cur);
+    advance_step_number<S>(ctr, cur, step, wave == 0 && threadIdx.x == 0);
     int x, y, z;
     if (!wave_cell(gd, wave, x, y, z)) return;
-    step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
+    step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z, step);
 }
 
 // K7 (diagnostic): the memory traffic of K1 alone -- every population read
@@ -296,16 +369,18 @@ __global__ void __launch_bounds__(step_max_threads<S>())
 template <int LAT, class S, int EQ, int FO>
 __global__ void __launch_bounds__(step_max_threads<S>())
     wall_step_kernel(const S *__restrict__ A, S *__restrict__ B, GridDims gd, ForceDesc fd,
-                     StepCoef co, WallDesc wd)
+                     StepCoef co, WallDesc wd, uint32_t *ctr, int cur)
 {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
                                                          (threadIdx.x >> 6));
+    const uint32_t step = step_number<S>(ctr, cur);
+    advance_step_number<S>(ctr, cur, step, wave == 0 && threadIdx.x == 0);
     int x, y, z;
     if (!wave_cell(gd, wave, x, y, z)) return;
     if (y < 3 || y >= gd.ny - 3)
-        step_cell<LAT, S, EQ, FO, true>(A, B, gd, fd, co, x, y, z, &wd);
+        step_cell<LAT, S, EQ, FO, true>(A, B, gd, fd, co, x, y, z, step, &wd);
     else
-        step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z);
+        step_cell<LAT, S, EQ, FO>(A, B, gd, fd, co, x, y, z, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,17 +424,20 @@ __global__ void __launch_bounds__(256)
         const int c = sd.cur ^ parity;
         const S *A = static_cast<const S *>(sd.pop[c]);
         S *B = static_cast<S *>(const_cast<void *>(sd.pop[c ^ 1]));
+        // the member's step number; its first tile's wavefront advances it
+        const uint32_t step = step_number<S>(sd.ctr, c);
+        advance_step_number<S>(sd.ctr, c, step, k == 0 && (threadIdx.x & 63u) == 0);
         if (x >= sd.gd.nx) continue;
         if constexpr (WALLS) {
             // a member between plates: its rows next to a plate as in K1c
             if (sd.wd.on && (y < 3 || y >= sd.gd.ny - 3)) {
                 WallDesc w = sd.wd;
                 w.par = c;
-                step_cell<LAT, S, EQ, FO, true>(A, B, sd.gd, sd.fd, sd.co, x, y, z, &w);
+                step_cell<LAT, S, EQ, FO, true>(A, B, sd.gd, sd.fd, sd.co, x, y, z, step, &w);
                 continue;
             }
         }
-        step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z);
+        step_cell<LAT, S, EQ, FO>(A, B, sd.gd, sd.fd, sd.co, x, y, z, step);
     }
 }
 
@@ -679,10 +757,11 @@ constexpr int resident_max_threads()
 template <int LAT, class S, int EQ, int FO, bool WALLS>
 __global__ void __launch_bounds__((resident_max_threads<S, WALLS>()))
     resident_kernel(S *__restrict__ P0, S *__restrict__ P1, GridDims gd, ForceDesc fd,
-                    StepCoef co, WallDesc wd, int nsteps)
+                    StepCoef co, WallDesc wd, int nsteps, uint32_t *ctr, int cur)
 {
     const int64_t N = gd.N;
     WallDesc w = wd;
+    const uint32_t step0 = step_number<S>(ctr, cur);
     for (int n = 0; n < nsteps; ++n) {
         const S *A = (n & 1) ? P1 : P0;
         S *B = (n & 1) ? P0 : P1;
@@ -691,10 +770,15 @@ __global__ void __launch_bounds__((resident_max_threads<S, WALLS>()))
             const int x = int(c % gd.nx);
             const int64_t row = c / gd.nx;
             const int y = int(row % gd.ny), z = int(row / gd.ny);
-            step_cell<LAT, S, EQ, FO, WALLS, true>(A, B, gd, fd, co, x, y, z, &w);
+            step_cell<LAT, S, EQ, FO, WALLS, true>(A, B, gd, fd, co, x, y, z,
+                                                   step0 + uint32_t(n), &w);
         }
         __syncthreads();
     }
+    // every lane read the counter before the first barrier: the last step's
+    // successor slot can be written now
+    advance_step_number<S>(ctr, cur ^ ((nsteps - 1) & 1), step0 + uint32_t(nsteps - 1),
+                           threadIdx.x == 0 && nsteps > 0);
 }
 
 // ---------------------------------------------------------------------------

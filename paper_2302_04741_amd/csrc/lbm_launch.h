@@ -46,7 +46,7 @@ hipError_t launch_step_ls(int eq, int fo, const void *A, void *B, const GridDims
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>), grid,
                            dim3(bx), 0, lc.stream, static_cast<const S *>(A),
-                           static_cast<S *>(B), gd, fd, co);
+                           static_cast<S *>(B), gd, fd, co, lc.ctr, lc.cur);
         return hipGetLastError();
     });
 }
@@ -141,7 +141,7 @@ hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const Gri
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
         hipLaunchKernelGGL((wall_step_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
                            grid, dim3(bx), 0, lc.stream, static_cast<const S *>(A),
-                           static_cast<S *>(B), gd, fd, co, lc.walls);
+                           static_cast<S *>(B), gd, fd, co, lc.walls, lc.ctr, lc.cur);
         return hipGetLastError();
     });
 }
@@ -162,12 +162,12 @@ hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &
             hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, true>), dim3(1),
                                dim3(threads(resident_max_threads<S, true>())), 0, lc.stream,
                                static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
-                               nsteps);
+                               nsteps, lc.ctr, lc.cur);
         else
             hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, false>), dim3(1),
                                dim3(threads(resident_max_threads<S, false>())), 0, lc.stream,
                                static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
-                               nsteps);
+                               nsteps, lc.ctr, lc.cur);
         return hipGetLastError();
     });
 }

@@ -153,7 +153,7 @@ def test_batch_rejects_stale_and_mixed_members(sim_mod):
         b.set([a, a])  # duplicate
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16dev"])
 def test_graph_replays_equal_eager_steps(sim_mod, storage):
     wl = workloads.random_smooth("D3Q39", (24, 20, 18), seed=4, force_kind="axis", g_amp=1e-3)
     stream = torch.cuda.Stream()
@@ -176,14 +176,15 @@ def test_graph_replays_equal_eager_steps(sim_mod, storage):
     torch.cuda.synchronize()
 
 
-def test_batch_graph_replays(sim_mod):
-    wls = mix("D2Q37", "f32", seed=7)
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_batch_graph_replays(sim_mod, storage):
+    wls = mix("D2Q37", storage, seed=7)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        refs = [sim_mod.from_workload(wl, storage="f32") for wl in wls]
+        refs = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
         bref = sim_mod.Batch(len(refs))
         bref.set(refs)
-        sims = [sim_mod.from_workload(wl, storage="f32") for wl in wls]
+        sims = [sim_mod.from_workload(wl, storage=storage) for wl in wls]
         b = sim_mod.Batch(len(sims))
         b.set(sims)
         g = sim_mod.Graph(b, 6)

@@ -22,7 +22,8 @@ def sim_mod():
 
 
 @pytest.mark.parametrize("lat,dims,storage", [("D2Q37", (200, 9, 1), "f64"),
-                                              ("D3Q39", (130, 6, 5), "f32")])
+                                              ("D3Q39", (130, 6, 5), "f32"),
+                                              ("D3Q39", (70, 9, 6), "f16dev")])
 def test_block_shape_does_not_change_bits(sim_mod, lat, dims, storage):
     wl = workloads.random_smooth(lat, dims, seed=2, force_kind="axis", g_amp=1e-3)
     pops = []
@@ -36,15 +37,18 @@ def test_block_shape_does_not_change_bits(sim_mod, lat, dims, storage):
         assert torch.equal(p, pops[0])
 
 
-def test_resume_from_checkpoint_is_bitwise(sim_mod):
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_resume_from_checkpoint_is_bitwise(sim_mod, storage):
+    """With F16 storage the step number keys the stochastic rounding:
+    setting the step count restores it."""
     wl = workloads.random_smooth("D3Q39", (12, 10, 8), seed=3, force_kind="uniform", g_amp=1e-3)
-    a = sim_mod.from_workload(wl, storage="f32")
+    a = sim_mod.from_workload(wl, storage=storage)
     a.step(9)
     ref = a.get_populations().clone()
-    b = sim_mod.from_workload(wl, storage="f32")
+    b = sim_mod.from_workload(wl, storage=storage)
     b.step(4)
     ck = b.get_populations().clone()
-    c = sim_mod.from_workload(wl, storage="f32")
+    c = sim_mod.from_workload(wl, storage=storage)
     c.set_populations(ck)
     c.step_count = 4
     c.step(5)
@@ -133,3 +137,39 @@ def test_pattern_pass_leaves_the_state(sim_mod, storage):
     assert torch.equal(a.get_populations(), b.get_populations())
     with pytest.raises(Exception):
         a.pattern_pass(-1)
+
+
+def test_f16_stochastic_rounding_is_unbiased(sim_mod):
+    """F16 storage rounds stochastically: on a uniform gas at rest
+    (rho = 1.003, theta = 1, no force) every step stores h_i = w_i (rho - 1),
+    a value binary16 cannot hold.  Round-to-nearest would make the same error
+    in every cell, and the total mass would drift by N times it per step;
+    with zero-mean rounding the mass performs a random walk whose standard
+    deviation after n steps is at most sqrt(n sum over stored values of
+    (ulp/2)^2) (each value's rounding variance is p(1 - p) ulp^2 <= ulp^2/4).
+    The measured drift must stay within 6 of those deviations, a bound the
+    nearest rounding of these values would exceed many times over."""
+    from paper_2302_04741_amd import _lib
+
+    n, steps, drho = 256, 100, 3e-3
+    N = n * n
+    s = sim_mod.Sim("D2Q37", (n, n), 0.8, np.full(N, 1.0 + drho), np.zeros((2, N)),
+                    np.ones(N), storage="f16dev")
+    m0 = s.totals()[0]
+    s.step(steps)
+    m1 = s.totals()[0]
+    _, w, _ = _lib.lattice_table("D2Q37")
+    k = np.round(-np.log2(w))
+    # the values stored each step (scaled), their half spacing, and the
+    # spacing in units of f
+    v = np.abs(w * drho * 2.0 ** k)
+    ulp = 2.0 ** (np.floor(np.log2(v)) - 10)
+    sigma = np.sqrt(steps * N * ((ulp * 2.0 ** -k / 2.0) ** 2).sum())
+    # what round-to-nearest would do: the same error in every cell, every step
+    rn = np.abs(np.float16(v) - v)  # |RN(v) - v| in scaled units (v > 0)
+    rn_drift = steps * N * np.abs((np.sign(np.float16(v) - v) * rn * 2.0 ** -k).sum())
+    drift = abs(m1 - m0)
+    print("mass drift %.3e, SR bound 6 sigma %.3e, RN drift would be %.3e"
+          % (drift, 6 * sigma, rn_drift), flush=True)
+    assert drift <= 6.0 * sigma
+    assert rn_drift >= 20.0 * 6.0 * sigma

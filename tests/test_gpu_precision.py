@@ -6,15 +6,24 @@ GPU FP64 path, whose parity with the oracle the parity tests establish.
 
 The a3_F heat-flux correction of the paper (Sec. 2, q_err: the heat flux that
 dropping the third-moment force term adds) is measured as
-dq = q(force order 2) - q(force order 4), projected on the sin/cos(2 pi y/L)
-modes; FP32 storage must reproduce the dominant FP64 mode within 10%.
+dq = q(force order 2) - q(force order 4), two runs from the same initial
+state, projected on the Fourier modes the workload drives (sin/cos(2 pi y/L);
+in 3-D also their products with sin/cos(2 pi z/L), where the Kolmogorov
+case's correction lives), at step 2000 and averaged over 8 snapshots 25 steps
+apart from there (the time average takes out rounding noise that decorrelates
+between snapshots; FP64 is averaged the same way).
 
-Bars (about 5x the values measured on an MI355X):
+Bars (FP32 about 5x the values measured on an MI355X):
   FP32: rho 2e-4, u 2e-3, theta 5e-4 relative (as in the parity tests), q 1e-2
-        relative to max|q|.
-  F16 : rho 3e-3, u 2e-2, theta 2e-3; q is not bounded: with 11-bit half
-        rounding of deviations that reach ~25% of w_i, q is off by 1e-2..3e-1
-        and dq is not resolved (recorded, not asserted).
+        relative to max|q|; the dominant dq mode within 10% of FP64's.
+  F16 (stochastic rounding): rho 3e-3, u 2e-2, theta 2e-3; the time-averaged
+        dq mode within 10% of FP64's on every workload (measured 3.3% on the
+        256^2 shear, 4.7% on 1024^2, 0.06% on the Kolmogorov flow; at a single
+        snapshot 18.6%, 2.7% and 0.07%).  q pointwise is not bounded: the half
+        rounding of deviations that reach ~25% of w_i leaves noise of
+        1e-2..5e-1 of max|q| in single cells.  With round-to-nearest stores
+        (measured with a library variant) the shear workloads' dq came out
+        37-217% off, twice with the wrong sign.
 """
 import math
 
@@ -38,23 +47,53 @@ def sim_mod():
     return sim
 
 
+SNAPS, EVERY = 8, 25
+
+
 def run(sim_mod, wl, storage, force_order):
+    """Moments and heat flux at STEPS, and the heat-flux modes averaged over
+    SNAPS snapshots EVERY steps apart from STEPS on."""
     wl.force_order = force_order
     s = sim_mod.from_workload(wl, storage=storage)
     s.step(STEPS)
     m = gpu_moments(s)
     q = to_host(s.heat_flux())
+    avg = modes(q, wl)
+    for _ in range(SNAPS - 1):
+        s.step(EVERY)
+        avg = avg + modes(to_host(s.heat_flux()), wl)
     s.close()
-    return m, q
+    return m, q, avg / SNAPS
+
+
+def oracle_runs(oracle_mod, wl):
+    """The same quantities from the CPU oracle."""
+    o = oracle_run(oracle_mod, wl, STEPS)
+    m, q = o.moments(), o.heat_flux()
+    avg = modes(q, wl)
+    for _ in range(SNAPS - 1):
+        o.step(EVERY)
+        avg = avg + modes(o.heat_flux(), wl)
+    return m, q, avg / SNAPS
 
 
 def modes(q, wl):
+    """Amplitudes of the lowest Fourier modes the workloads drive: sin and
+    cos(2 pi y/ny) of every component, and in 3-D also their products with
+    sin and cos(2 pi z/nz) (the Kolmogorov force varies in z, the temperature
+    in y, so its a3_F heat flux lives on the product modes)."""
     nx, ny, nz = wl.dims
-    y = (np.arange(wl.ncell) // nx) % ny
+    cell = np.arange(wl.ncell)
+    y = (cell // nx) % ny
+    z = cell // (nx * ny)
+    basis = [f(2 * math.pi * y / ny) for f in (np.sin, np.cos)]
+    if nz > 1:
+        basis += [f(2 * math.pi * y / ny) * g(2 * math.pi * z / nz)
+                  for f in (np.sin, np.cos) for g in (np.sin, np.cos)]
     out = []
     for a in range(q.shape[0]):
-        for f in (np.sin, np.cos):
-            out.append(2.0 / wl.ncell * (q[a] * f(2 * math.pi * y / ny)).sum())
+        for b in basis:
+            out.append((q[a] * b).sum() / (b * b).sum())
     return np.array(out)
 
 
@@ -67,37 +106,45 @@ WORKLOADS = {
 }
 
 
+# bar on the time-averaged a3_F dq mode, relative to FP64
+TOL_DQ = {("f32", "shear256"): 0.10, ("f32", "shear1024"): 0.10, ("f32", "kolmogorov256"): 0.10,
+          ("f16dev", "shear256"): 0.10, ("f16dev", "shear1024"): 0.10,
+          ("f16dev", "kolmogorov256"): 0.10}
+
+
 @pytest.fixture(scope="module")
 def references(sim_mod, oracle_mod):
     refs = {}
     for name, make in WORKLOADS.items():
         if name == "shear256":
-            wl = make(4)
-            o = oracle_run(oracle_mod, wl, STEPS)
-            ref4 = (o.moments(), o.heat_flux())
-            o2 = oracle_run(oracle_mod, make(2), STEPS)
-            q2 = o2.heat_flux()
+            m4, q4, a4 = oracle_runs(oracle_mod, make(4))
+            _, q2, a2 = oracle_runs(oracle_mod, make(2))
         else:
-            ref4 = run(sim_mod, make(4), "f64", 4)
-            q2 = run(sim_mod, make(2), "f64", 2)[1]
-        refs[name] = (ref4, modes(q2 - ref4[1], make(4)))
+            m4, q4, a4 = run(sim_mod, make(4), "f64", 4)
+            _, q2, a2 = run(sim_mod, make(2), "f64", 2)
+        refs[name] = ((m4, q4), modes(q2 - q4, make(4)), a2 - a4)
     return refs
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 def test_reduced_precision_errors(sim_mod, references, name, storage):
-    (ref_m, ref_q), ref_dq = references[name]
-    m, q = run(sim_mod, WORKLOADS[name](4), storage, 4)
+    (ref_m, ref_q), ref_dq, ref_avg = references[name]
+    m, q, a4 = run(sim_mod, WORKLOADS[name](4), storage, 4)
     errs = rel_err(m, ref_m)
     eq = np.abs(q - ref_q).max() / np.abs(ref_q).max()
-    _, q2 = run(sim_mod, WORKLOADS[name](2), storage, 2)
+    _, q2, a2 = run(sim_mod, WORKLOADS[name](2), storage, 2)
     dq = modes(q2 - q, WORKLOADS[name](4))
     k = int(np.argmax(np.abs(ref_dq)))
     edq = abs(dq[k] - ref_dq[k]) / abs(ref_dq[k])
+    ka = int(np.argmax(np.abs(ref_avg)))
+    edq_avg = abs((a2 - a4)[ka] - ref_avg[ka]) / abs(ref_avg[ka])
     print("%s %s after %d steps: rho %.2e u %.2e theta %.2e q %.2e | a3_F dq mode %.3e vs %.3e "
-          "(rel %.2e)" % (name, storage, STEPS, *errs, eq, dq[k], ref_dq[k], edq), flush=True)
+          "(rel %.2e); averaged over %d snapshots %.3e vs %.3e (rel %.2e)"
+          % (name, storage, STEPS, *errs, eq, dq[k], ref_dq[k], edq, SNAPS, (a2 - a4)[ka],
+             ref_avg[ka], edq_avg), flush=True)
     assert all(e <= t for e, t in zip(errs, TOL[storage])), errs
     if storage == "f32":
         assert eq <= TOL_Q32
-        assert edq <= 0.10  # the a3_F correction is resolved
+        assert edq <= 0.10  # the a3_F correction is resolved at one snapshot
+    assert edq_avg <= TOL_DQ[(storage, name)]  # and on the time average
