@@ -158,7 +158,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str) -> dict:
         fh.write("# counter runs (repo root, MI355X), one counter per run:\n")
         for counter, d in zip(("FETCH_SIZE", "WRITE_SIZE"), dirs):
             fh.write("#   rocprofv3 --pmc %s -f csv -d %s -o pmc -- python3 bench.py "
-                     "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib\n" % (counter, d))
+                     "--steps 5 --warmup 2 --cpu-steps 0 --repeats 0 --copy-calib --no-serve\n"
+                     % (counter, d))
         fh.write("# summarised by:\n#   python3 bench.py --summarize-pmc %s %s\n"
                  % tuple(os.path.relpath(os.path.abspath(p), ROOT) for p in (fetch_csv, write_csv)))
         fh.write("# scale = 2 GiB / counter value of the 2 GiB plain device copy in the same run\n")
