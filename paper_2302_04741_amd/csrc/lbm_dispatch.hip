@@ -97,32 +97,43 @@ hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLa
     return hipErrorInvalidValue;
 }
 
+#define LBM_BY_STORAGE(CALL)                                   \
+    if (lat == 0 && storage == 0) return CALL(0, double);      \
+    if (lat == 0 && storage == 1) return CALL(0, float);       \
+    if (lat == 0 && storage == 2) return CALL(0, __half);      \
+    if (lat == 1 && storage == 0) return CALL(1, double);      \
+    if (lat == 1 && storage == 1) return CALL(1, float);       \
+    if (lat == 1 && storage == 2) return CALL(1, __half);      \
+    return hipErrorInvalidValue
+
 hipError_t launch_init(int lat, int storage, int eq, int fo, const double *rho, const double *u,
                        const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
                        const StepCoef &co, const LaunchCfg &lc)
 {
-    if (lat == 0) return launch_init_l<0>(storage, eq, fo, rho, u, theta, A, gd, fd, co, lc);
-    if (lat == 1) return launch_init_l<1>(storage, eq, fo, rho, u, theta, A, gd, fd, co, lc);
-    return hipErrorInvalidValue;
+#define LBM_INIT(L, S) launch_init_ls<L, S>(eq, fo, rho, u, theta, A, gd, fd, co, lc)
+    LBM_BY_STORAGE(LBM_INIT);
+#undef LBM_INIT
 }
 
 hipError_t launch_moments(int lat, int storage, const void *A, double *rho, double *u,
                           double *theta, const GridDims &gd, const ForceDesc &fd,
                           const StepCoef &co, const LaunchCfg &lc)
 {
-    if (lat == 0) return launch_moments_l<0>(storage, A, rho, u, theta, gd, fd, co, lc);
-    if (lat == 1) return launch_moments_l<1>(storage, A, rho, u, theta, gd, fd, co, lc);
-    return hipErrorInvalidValue;
+#define LBM_MOM(L, S) launch_moments_ls<L, S>(A, rho, u, theta, gd, fd, co, lc)
+    LBM_BY_STORAGE(LBM_MOM);
+#undef LBM_MOM
 }
 
 hipError_t launch_heat_flux(int lat, int storage, int eq, int fo, const void *A, double *q,
                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
                             const LaunchCfg &lc)
 {
-    if (lat == 0) return launch_heat_flux_l<0>(storage, eq, fo, A, q, gd, fd, co, lc);
-    if (lat == 1) return launch_heat_flux_l<1>(storage, eq, fo, A, q, gd, fd, co, lc);
-    return hipErrorInvalidValue;
+#define LBM_HF(L, S) launch_heat_flux_ls<L, S>(eq, fo, A, q, gd, fd, co, lc)
+    LBM_BY_STORAGE(LBM_HF);
+#undef LBM_HF
 }
+
+#undef LBM_BY_STORAGE
 
 hipError_t launch_totals(int lat, int storage, const void *A, double *partials, double *out_dev,
                          const GridDims &gd, const StepCoef &co, hipStream_t stream)

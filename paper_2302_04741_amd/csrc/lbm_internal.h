@@ -644,18 +644,17 @@ hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, in
 template <int LAT>
 hipError_t launch_wall_mass_l(int storage, const void *A, const GridDims &gd, const StepCoef &co,
                               const LaunchCfg &lc);
-template <int LAT>
-hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
-                         const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
-                         const StepCoef &co, const LaunchCfg &lc);
-template <int LAT>
-hipError_t launch_moments_l(int storage, const void *A, double *rho, double *u, double *theta,
-                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                            const LaunchCfg &lc);
-template <int LAT>
-hipError_t launch_heat_flux_l(int storage, int eq, int fo, const void *A, double *q,
-                              const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                              const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_init_ls(int eq, int fo, const double *rho, const double *u, const double *theta,
+                          void *A, const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                          const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_moments_ls(const void *A, double *rho, double *u, double *theta,
+                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                             const LaunchCfg &lc);
+template <int LAT, class S>
+hipError_t launch_heat_flux_ls(int eq, int fo, const void *A, double *q, const GridDims &gd,
+                               const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
 template <int LAT>
 hipError_t launch_totals_l(int storage, const void *A, double *partials, double *out_dev,
                            const GridDims &gd, const StepCoef &co, hipStream_t stream);

@@ -442,108 +442,70 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// runtime-storage access for the kernels off the step path
-// (storage: 0 = double, 1 = float, 2 = F16 deviations); all values are h_i
+// kernels off the step path: one thread per cell, blocks along x of one grid
+// row (y and z uniform over the block), arithmetic in the storage's own
+// precision (FP64 for FP64 storage, FP32 for FP32 and F16 storage; the
+// fields handed in and out stay FP64)
 // ---------------------------------------------------------------------------
-template <class L, int I>
-__device__ __forceinline__ double load_any(const void *A, int storage, int64_t idx)
+// h_i (unscaled) of the state in A at (x, y, z), the plates' emission in
+// place of sources behind them.
+template <class L, class S, class T>
+__device__ __forceinline__ void gather_state(const S *__restrict__ A, const GridDims &gd, int x,
+                                             int y, int z, T (&h)[L::Q], const WallDesc &wd,
+                                             double rho0)
 {
-    if (storage == 0) return static_cast<const double *>(A)[idx];
-    if (storage == 1) return double(static_cast<const float *>(A)[idx]);
-    return Codec<L, __half>::template load<I, double>(static_cast<const __half *>(A)[idx]);
-}
-
-template <class L, int I>
-__device__ __forceinline__ void store_any(void *A, int storage, int64_t idx, double h)
-{
-    if (storage == 0) static_cast<double *>(A)[idx] = h;
-    else if (storage == 1) static_cast<float *>(A)[idx] = float(h);
-    else static_cast<__half *>(A)[idx] = Codec<L, __half>::template store<I, double>(h);
-}
-
-template <class L>
-__device__ __forceinline__ void gather_any(const void *A, int storage, const GridDims &gd, int x,
-                                           int y, int z, double (&h)[L::Q],
-                                           const WallDesc &wd, double rho0)
-{
-    const bool near = wd.on && (y < 3 || y >= gd.ny - 3);
-    int xs[7], ys[7], zs[7];
-#pragma unroll
-    for (int d = 0; d < 7; ++d) {
-        xs[d] = wrap3(x - (d - 3), gd.nx);
-        ys[d] = wrap3(y - (d - 3), gd.ny);
-        zs[d] = (L::D == 3) ? wrap3(z - (d - 3), gd.nz) : 0;
-    }
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
-        if (near && (y - cy < 0 || y - cy >= gd.ny)) {
-            h[i] = wall_emitted<L>(wd, gd, i, L::wshell(L::shell(i)), rho0, x, y, z);
-            return;
-        }
-        const int64_t idx =
-            int64_t(i) * gd.P + (int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px + xs[cx + 3];
-        h[i] = load_any<L, i>(A, storage, idx);
-    });
-}
-
-__device__ __forceinline__ void force_any(const ForceDesc &fd, int storage, const GridDims &gd,
-                                          int D, int x, int y, int z, int64_t cell, double g[3])
-{
-    if (storage == 0) {
-        if (D == 2) load_force<double, double, 2>(fd, gd, x, y, z, cell, g);
-        else load_force<double, double, 3>(fd, gd, x, y, z, cell, g);
-    } else {
-        if (D == 2) load_force<float, double, 2>(fd, gd, x, y, z, cell, g);
-        else load_force<float, double, 3>(fd, gd, x, y, z, cell, g);
-    }
+    if (wd.on && (y < 3 || y >= gd.ny - 3))  // uniform over the block
+        gather<L, S, T, true>(A, gd, x, y, z, h, &wd, rho0);
+    else
+        gather<L, S, T>(A, gd, x, y, z, h);
 }
 
 // ---------------------------------------------------------------------------
-// K2: initial state f~ = f0 - F/2 (sigma = 0), computed in FP64, stored as
-// h = f~ - w rho0 and scattered so that the pull gather of the first step
-// finds h_i(x) at A[i][x - c_i].
+// K2: initial state f~ = f0 - F/2 (sigma = 0), stored as h = f~ - w rho0 and
+// scattered so that the pull gather of the first step finds h_i(x) at
+// A[i][x - c_i].
 // ---------------------------------------------------------------------------
-template <int LAT, int EQ, int FO>
+template <int LAT, class S, int EQ, int FO>
 __global__ void __launch_bounds__(256)
     init_kernel(const double *__restrict__ rho, const double *__restrict__ u,
-                const double *__restrict__ theta, void *__restrict__ A, int storage, GridDims gd,
-                ForceDesc fd, StepCoef co, WallDesc wd)
+                const double *__restrict__ theta, S *__restrict__ A, GridDims gd, ForceDesc fd,
+                StepCoef co, WallDesc wd)
 {
     using L = Lattice<LAT>;
+    using T = typename ArithOf<S>::type;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= gd.nx) return;
     const int64_t N = gd.N;
     const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
 
-    double g[3];
-    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
-    CellState<double> cs;
-    cs.rho = rho[cell];
-    cs.drho = cs.rho - co.rho0;
-    cs.th = theta[cell];
+    T g[3];
+    load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
+    CellState<T> cs;
+    cs.rho = T(rho[cell]);
+    cs.drho = T(rho[cell] - co.rho0);  // the deviation rounded once
+    cs.th = T(theta[cell]);
     for (int a = 0; a < 3; ++a) {
-        cs.ub[a] = (a < L::D) ? u[int64_t(a) * N + cell] : 0.0;
+        cs.ub[a] = (a < L::D) ? T(u[int64_t(a) * N + cell]) : T(0);
         cs.g[a] = g[a];
-        for (int b = 0; b < 3; ++b) cs.sig[a][b] = 0.0;
+        for (int b = 0; b < 3; ++b) cs.sig[a][b] = T(0);
     }
     constexpr int FOI = FO == 4 ? 3 : FO;  // sigma = 0 at the start
     // h = w (rho - rho0) + (f0 - w rho) - F/2
-    combo_pairs<L, double, EQ, FOI, true>(cs, 1.0, -0.5, [&](auto IP, auto IM, double ev,
-                                                            double od) {
+    combo_pairs<L, T, EQ, FOI, true>(cs, T(1), T(-0.5), [&](auto IP, auto IM, T ev, T od) {
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip));
-        auto put = [&](auto II, double v) {
+        auto put = [&](auto II, T v) {
             constexpr int i = decltype(II)::value;
+            const S sv = Codec<L, S>::template store<i, T>(v);
             if (wd.on) {
                 // with plates: a population arriving from behind a plate has no
                 // slot (the plate emits it); one about to stream into a plate
                 // stays in its own node's slot
                 if (y + L::c(i, 1) < 0 || y + L::c(i, 1) >= gd.ny) {
                     const int64_t own = (int64_t(z) * gd.ny + y) * gd.px + x;
-                    store_any<L, i>(A, storage, int64_t(i) * gd.P + own, v);
+                    A[int64_t(i) * gd.P + own] = sv;
                 }
                 if (y - L::c(i, 1) < 0 || y - L::c(i, 1) >= gd.ny) return;
             }
@@ -551,86 +513,107 @@ __global__ void __launch_bounds__(256)
             const int yd = wrap3(y - L::c(i, 1), gd.ny);
             const int zd = (L::D == 3) ? wrap3(z - L::c(i, 2), gd.nz) : 0;
             const int64_t dst = (int64_t(zd) * gd.ny + yd) * gd.px + xd;
-            store_any<L, i>(A, storage, int64_t(i) * gd.P + dst, v);
+            A[int64_t(i) * gd.P + dst] = sv;
         };
-        const double base = w * cs.drho;
+        const T base = T(w) * cs.drho;
         put(std::integral_constant<int, ip>{}, base + (ev + od));
         if constexpr (im >= 0) put(std::integral_constant<int, im>{}, base + (ev - od));
     });
 }
 
 // ---------------------------------------------------------------------------
-// K3: physical moments (FP64)
+// K3: physical moments rho, u + g/2, theta of the state
 // ---------------------------------------------------------------------------
-template <int LAT>
+template <int LAT, class S>
 __global__ void __launch_bounds__(256)
-    moments_kernel(const void *__restrict__ A, int storage, double *__restrict__ rho,
-                   double *__restrict__ u, double *__restrict__ theta, GridDims gd, ForceDesc fd,
-                   StepCoef co, WallDesc wd)
+    moments_kernel(const S *__restrict__ A, double *__restrict__ rho, double *__restrict__ u,
+                   double *__restrict__ theta, GridDims gd, ForceDesc fd, StepCoef co,
+                   WallDesc wd)
 {
     using L = Lattice<LAT>;
+    using T = typename ArithOf<S>::type;
+    using C = Codec<L, S>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= gd.nx) return;
     const int64_t N = gd.N;
     const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
-    double h[L::Q];
-    gather_any<L>(A, storage, gd, x, y, z, h, wd, co.rho0);
-    double g[3];
-    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
-    const RawSums<double> rs = raw_sums<L, double>(h);
-    CellState<double> cs;
-    finish_moments<L, double, false>(rs, g, co, cs);
-    if (rho) rho[cell] = cs.rho;
-    if (theta) theta[cell] = cs.th;
+    T h[L::Q];  // as stored (scaled for F16): raw_sums takes the scale out
+    gather_state<L, S, T>(A, gd, x, y, z, h, wd, co.rho0);
+    T g[3];
+    load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
+    const RawSums<T> rs = raw_sums<L, T, C>(h);
+    CellState<T> cs;
+    finish_moments<L, T, false>(rs, g, co, cs);
+    if (rho) rho[cell] = double(cs.rho);
+    if (theta) theta[cell] = double(cs.th);
     if (u)
-        for (int a = 0; a < L::D; ++a) u[int64_t(a) * N + cell] = cs.ub[a];
+        for (int a = 0; a < L::D; ++a) u[int64_t(a) * N + cell] = double(cs.ub[a]);
 }
 
 // ---------------------------------------------------------------------------
-// K5: heat flux of the physical distribution (FP64)
-//   f = f0 + cf (f~ - f0 + F/2) = cf f~ + (1 - cf) f0 + (cf/2) F
-//     = w rho0 + cf h + (1 - cf) w drho + [(1 - cf)(f0 - w rho) + (cf/2) F]
+// K5: heat flux q = 1/2 sum_i f_i |xi_i - u|^2 (xi_i - u) of the physical
+// distribution f = f0 + cf (f~ - f0 + F/2).  With the equilibrium of order
+// N >= 3 the rule reproduces the Maxwellian's moments up to order N + 3, so
+// sum_i f0_i |c_i|^2 c_i (c = xi - u) is the Maxwellian's third central
+// moment, zero: q = 1/2 sum_i (f_i - f0_i) |c_i|^2 c_i, a sum of small terms
+//   f - f0 = cf (h - w drho) - cf (f0 - w rho) + (cf/2) F.
+// For N = 2 the equilibrium's own part is added, sum_i f0_i |c_i|^2 c_i =
+// -rho u (D + 2 + |u|^2) (the rule's moments to degree 3) + sum_i (f0 - w rho)_i |c_i|^2 c_i.
 // ---------------------------------------------------------------------------
-template <int LAT, int EQ, int FO>
+template <int LAT, class S, int EQ, int FO>
 __global__ void __launch_bounds__(256)
-    heatflux_kernel(const void *__restrict__ A, int storage, double *__restrict__ q, GridDims gd,
-                    ForceDesc fd, StepCoef co, WallDesc wd)
+    heatflux_kernel(const S *__restrict__ A, double *__restrict__ q, GridDims gd, ForceDesc fd,
+                    StepCoef co, WallDesc wd)
 {
     using L = Lattice<LAT>;
+    using T = typename ArithOf<S>::type;
+    using C = Codec<L, S>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= gd.nx) return;
     const int64_t N = gd.N;
     const int64_t cell = (int64_t(z) * gd.ny + y) * gd.nx + x;
-    double h[L::Q];
-    gather_any<L>(A, storage, gd, x, y, z, h, wd, co.rho0);
-    double g[3];
-    force_any(fd, storage, gd, L::D, x, y, z, cell, g);
-    const RawSums<double> rs = raw_sums<L, double>(h);
-    CellState<double> cs;
-    finish_moments<L, double, FO == 4>(rs, g, co, cs);
-    const double cf = cs.cf;
-    double qa[3] = {0.0, 0.0, 0.0};
-    auto acc = [&](auto II, double fp) {
+    T h[L::Q];
+    gather_state<L, S, T>(A, gd, x, y, z, h, wd, co.rho0);
+    T g[3];
+    load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
+    const RawSums<T> rs = raw_sums<L, T, C>(h);
+    CellState<T> cs;
+    finish_moments<L, T, FO == 4>(rs, g, co, cs);
+    static_for<0, L::Q>([&](auto I) {  // the deviations themselves (exact: powers of two)
+        constexpr int i = decltype(I)::value;
+        constexpr double inv = 1.0 / C::template scale<i>();
+        if constexpr (inv != 1.0) h[i] *= T(inv);
+    });
+    const T cf = cs.cf;
+    T qa[3] = {T(0), T(0), T(0)};
+    auto acc = [&](auto II, T d) {
         constexpr int i = decltype(II)::value;
-        double cv[3], cc = 0.0;
+        T cv[3], cc = T(0);
         for (int a = 0; a < L::D; ++a) {
-            cv[a] = L::R * double(L::c(i, a)) - cs.ub[a];
+            cv[a] = T(L::R * double(L::c(i, a))) - cs.ub[a];
             cc += cv[a] * cv[a];
         }
-        for (int a = 0; a < L::D; ++a) qa[a] += fp * cc * cv[a];
+        for (int a = 0; a < L::D; ++a) qa[a] += d * cc * cv[a];
     };
-    combo_pairs<L, double, EQ, FO, true>(
-        cs, 1.0 - cf, 0.5 * cf, [&](auto IP, auto IM, double ev, double od) {
-            constexpr int ip = decltype(IP)::value;
-            constexpr int im = decltype(IM)::value;
-            constexpr double w = L::wshell(L::shell(ip));
-            const double base = w * co.rho0 + (1.0 - cf) * w * cs.drho;
-            acc(IP, base + cf * h[ip] + (ev + od));
-            if constexpr (im >= 0) acc(IM, base + cf * h[im] + (ev - od));
+    combo_pairs<L, T, EQ, FO, true>(cs, -cf, T(0.5) * cf, [&](auto IP, auto IM, T ev, T od) {
+        constexpr int ip = decltype(IP)::value;
+        constexpr int im = decltype(IM)::value;
+        constexpr double w = L::wshell(L::shell(ip));
+        acc(IP, cf * (h[ip] - T(w) * cs.drho) + (ev + od));
+        if constexpr (im >= 0) acc(IM, cf * (h[im] - T(w) * cs.drho) + (ev - od));
+    });
+    if constexpr (EQ == 2) {
+        T u2 = T(0);
+        for (int a = 0; a < L::D; ++a) u2 += cs.ub[a] * cs.ub[a];
+        for (int a = 0; a < L::D; ++a) qa[a] -= cs.rho * cs.ub[a] * (T(L::D + 2) + u2);
+        combo_pairs<L, T, 2, 1, true>(cs, T(1), T(0), [&](auto IP, auto IM, T ev, T od) {
+            acc(IP, ev + od);
+            if constexpr (decltype(IM)::value >= 0) acc(IM, ev - od);
         });
-    for (int a = 0; a < L::D; ++a) q[int64_t(a) * N + cell] = 0.5 * qa[a];
+    }
+    for (int a = 0; a < L::D; ++a) q[int64_t(a) * N + cell] = double(T(0.5) * qa[a]);
 }
 
 // ---------------------------------------------------------------------------

@@ -89,41 +89,40 @@ hipError_t launch_multi_step_ls(int eq, int fo, const BatchLaunch &bl)
     });
 }
 
-template <int LAT>
-hipError_t launch_init_l(int storage, int eq, int fo, const double *rho, const double *u,
-                         const double *theta, void *A, const GridDims &gd, const ForceDesc &fd,
-                         const StepCoef &co, const LaunchCfg &lc)
+template <int LAT, class S>
+hipError_t launch_init_ls(int eq, int fo, const double *rho, const double *u, const double *theta,
+                          void *A, const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                          const LaunchCfg &lc)
 {
     const int bx = block_for(gd, 256);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
-        hipLaunchKernelGGL((init_kernel<LAT, decltype(E)::value, decltype(O)::value>),
-                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, rho, u, theta, A, storage,
-                           gd, fd, co, lc.walls);
+        hipLaunchKernelGGL((init_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, rho, u, theta,
+                           static_cast<S *>(A), gd, fd, co, lc.walls);
         return hipGetLastError();
     });
 }
 
-template <int LAT>
-hipError_t launch_moments_l(int storage, const void *A, double *rho, double *u, double *theta,
-                            const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                            const LaunchCfg &lc)
+template <int LAT, class S>
+hipError_t launch_moments_ls(const void *A, double *rho, double *u, double *theta,
+                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
+                             const LaunchCfg &lc)
 {
     const int bx = block_for(gd, 256);
-    hipLaunchKernelGGL((moments_kernel<LAT>), cell_grid(gd, bx), dim3(bx), 0, lc.stream, A,
-                       storage, rho, u, theta, gd, fd, co, lc.walls);
+    hipLaunchKernelGGL((moments_kernel<LAT, S>), cell_grid(gd, bx), dim3(bx), 0, lc.stream,
+                       static_cast<const S *>(A), rho, u, theta, gd, fd, co, lc.walls);
     return hipGetLastError();
 }
 
-template <int LAT>
-hipError_t launch_heat_flux_l(int storage, int eq, int fo, const void *A, double *q,
-                              const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                              const LaunchCfg &lc)
+template <int LAT, class S>
+hipError_t launch_heat_flux_ls(int eq, int fo, const void *A, double *q, const GridDims &gd,
+                               const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc)
 {
     const int bx = block_for(gd, 256);
     return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
-        hipLaunchKernelGGL((heatflux_kernel<LAT, decltype(E)::value, decltype(O)::value>),
-                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, A, storage, q, gd, fd, co,
-                           lc.walls);
+        hipLaunchKernelGGL((heatflux_kernel<LAT, S, decltype(E)::value, decltype(O)::value>),
+                           cell_grid(gd, bx), dim3(bx), 0, lc.stream, static_cast<const S *>(A),
+                           q, gd, fd, co, lc.walls);
         return hipGetLastError();
     });
 }

@@ -20,11 +20,14 @@ Per configuration:
     FP64 within the same bars as the full scheme.  The full-size difference of
     the two schemes after 5000 steps (rho, u, theta and q, FP64) is printed.
     Its temperature part (2.5e-7 to 1.6e-6 of theta at dtheta 0.02, 1.2e-5 to
-    1.4e-5 at dtheta 0.1) is resolved by FP32 only where it exceeds FP32's own
-    coherent theta drift over the run (7e-6 to 1.4e-4): at dtheta 0.1 the FP32
-    difference of the two schemes on its dominant y-mode is within 15% of
-    FP64's (measured 0.9-7.3%); at dtheta 0.02 it is not (16-95%), which the
-    test records as the scheme difference staying below 3x the FP32 error.
+    1.4e-5 at dtheta 0.1) is resolved by FP32 only where it is comparable to
+    FP32's own coherent theta drift over the run (7e-6 to 1.4e-4): where the
+    scheme difference is at least 0.4x that drift (tau-hat 0.9, dtheta 0.1) the
+    FP32 difference of the two schemes on its dominant y-mode is within 15% of
+    FP64's (measured 0.9-1.4%); elsewhere the drift is 2.5x to 60x the
+    difference and the mode is not resolved (5-95%, depending on how the
+    rounding of each run falls), which the test records as the scheme
+    difference staying below 3x the FP32 error.
 
 Measured values are printed; the bars are about 3x above the largest of them.
 """
@@ -163,7 +166,7 @@ def test_thermal_shear_1024_sweep(sim_mod, tau, dth, ma):
     assert all(x <= t for x, t in zip(e2, TOL32)), e2
     assert eq2 <= TOL_Q32
     assert np.abs(dth64).max() > 0.0
-    if dth >= 0.1:
+    if np.abs(dth64).max() >= 0.4 * err32_th:
         assert p_th <= 0.15
     else:
         # below FP32's resolution over 5000 steps (the 50-step heat-flux
