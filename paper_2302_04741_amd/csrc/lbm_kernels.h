@@ -322,12 +322,18 @@ __device__ __forceinline__ bool wave_cell(const GridDims &gd, uint32_t wave, int
     return x < gd.nx;
 }
 
+// Wavefronts per SIMD the compiler must leave room for (registers at most
+// 512 / 5 rounded down to the allocation granule): FP32 arithmetic fits five
+// without spills; left free, the F16 step's stochastic rounding led the
+// scheduler to a four-wave schedule (101 registers) that ran slower.  FP64
+// arithmetic needs more than 128 registers and is not constrained.
+template <class S> constexpr int step_min_waves() { return sizeof(S) == 8 ? 1 : 5; }
+
 template <int LAT, class S, int EQ, int FO>
-__global__ void __launch_bounds__(step_max_threads<S>()) step_kernel(const S *__restrict__ A,
-                                                                     S *__restrict__ B,
-                                                                     GridDims gd, ForceDesc fd,
-                                                                     StepCoef co, uint32_t *ctr,
-                                                                     int cur)
+__global__ void __launch_bounds__(step_max_threads<S>())
+    __attribute__((amdgpu_waves_per_eu(step_min_waves<S>(), 8)))
+    step_kernel(const S *__restrict__ A, S *__restrict__ B, GridDims gd, ForceDesc fd,
+                StepCoef co, uint32_t *ctr, int cur)
 {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) +
                                                          (threadIdx.x >> 6));
