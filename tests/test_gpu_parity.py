@@ -159,11 +159,19 @@ def test_uniform_acceleration_exact_on_gpu(sim_mod):
                                    rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("lat,dims,fo", [("D2Q37", (16, 12, 1), 4), ("D2Q37", (16, 12, 1), 2),
-                                          ("D3Q39", (6, 5, 7), 4), ("D3Q39", (6, 5, 7), 3)])
-def test_heat_flux_parity(sim_mod, oracle_mod, lat, dims, fo):
+@pytest.mark.parametrize("lat,dims,fo,eq", [("D2Q37", (16, 12, 1), 4, 4),
+                                             ("D2Q37", (16, 12, 1), 2, 4),
+                                             ("D3Q39", (6, 5, 7), 4, 3), ("D3Q39", (6, 5, 7), 3, 3),
+                                             ("D2Q37", (16, 12, 1), 4, 3),
+                                             ("D2Q37", (16, 12, 1), 4, 2),
+                                             ("D3Q39", (6, 5, 7), 2, 2)])
+def test_heat_flux_parity(sim_mod, oracle_mod, lat, dims, fo, eq):
+    """The kernel forms q from f - f0 (for equilibria of order >= 3 the rule
+    makes sum f0 |c|^2 c vanish; order 2 adds its closed form), the oracle
+    sums the physical f literally."""
     wl = workloads.random_smooth(lat, dims, seed=21, force_kind="axis", g_amp=1e-3,
                                  force_order=fo)
+    wl.eq_order = eq
     s = sim_mod.from_workload(wl)
     s.step(20)
     q = to_host(s.heat_flux())
@@ -284,3 +292,37 @@ def test_relaxation_time_extremes(sim_mod, oracle_mod, tau):
                                  amp_rho=0.005, amp_theta=0.01, force_kind="uniform",
                                  g_amp=1e-4)
     check_parity(sim_mod, oracle_mod, wl, 60)
+
+
+# bars about 6x the measured maxima (FP32: moments 3.3e-6, q 6.9e-5; F16: 3.1e-4, 3.3e-3)
+@pytest.mark.parametrize("storage,tol_m,tol_q", [("f32", 2e-5, 5e-4), ("f16dev", 2e-3, 2e-2)])
+def test_reduced_storage_fields_and_heat_flux(sim_mod, oracle_mod, storage, tol_m, tol_q):
+    """FP32 and F16 handles compute their initial state, moments and heat flux
+    in FP32 arithmetic: at step 0 the reported moments are the inputs to the
+    storage's precision, and after 20 steps the heat flux follows the FP64
+    oracle to the storage's precision (relative to max|q|)."""
+    wl = workloads.random_smooth("D2Q37", (40, 36, 1), seed=22, force_kind="axis", g_amp=1e-3)
+    s = sim_mod.from_workload(wl, storage=storage)
+    r, u, t = gpu_moments(s)
+    e0 = rel_err((r, u, t), (wl.rho, wl.u, wl.theta))
+    assert all(e <= tol_m for e in e0), e0
+    s.step(20)
+    q = to_host(s.heat_flux())
+    ora = oracle_run(oracle_mod, wl, 20)
+    eq = np.abs(q - ora.heat_flux()).max() / np.abs(ora.heat_flux()).max()
+    em = rel_err(gpu_moments(s), ora.moments())
+    print("%s: step-0 moments %s, after 20 steps moments %s, q %.2e" % (storage, e0, em, eq),
+          flush=True)
+    assert eq <= tol_q
+    assert all(e <= tol_m for e in em), em
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_totals_device_equals_totals(sim_mod, storage):
+    """lbm_totals_device enqueues the same reduction into device memory."""
+    wl = workloads.random_smooth("D3Q39", (20, 9, 7), seed=6, force_kind="uniform")
+    s = sim_mod.from_workload(wl, storage=storage)
+    s.step(3)
+    host = s.totals()
+    dev = s.totals_device().cpu().numpy()
+    assert np.array_equal(host, dev)
