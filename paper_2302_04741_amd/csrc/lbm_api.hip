@@ -619,7 +619,7 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.4.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.5.0"; }
 
 // ---------------------------------------------------------------------------
 // batches
