@@ -35,9 +35,10 @@ template <> struct ArithOf<__half> { using type = float; };
 // 32-bit finalizer of MurmurHash3 (Appleby) to spread every input bit over
 // the word.  The cell's stores then walk a 32-bit linear congruential
 // sequence from that key (Knuth's multiplier 6364136223846793005 reduced to
-// its low word, odd increment), each store taking the top 13 bits of the
-// current word: a uniform value below 2^13.  Nothing depends on the launch
-// shape, the batch or the other members.
+// its low word, odd increment), each store taking the current word whole as
+// the seed of its conversion (half_sr reads its top 13 bits, the sequence's
+// best ones).  Nothing depends on the launch shape, the batch or the other
+// members.
 __device__ __forceinline__ uint32_t sr_key(uint32_t cell, uint32_t step)
 {
     uint32_t h = cell * 0x9E3779B1u + step * 0x85EBCA77u;
@@ -50,9 +51,9 @@ __device__ __forceinline__ uint32_t sr_key(uint32_t cell, uint32_t step)
 }
 struct SrStream {
     uint32_t x;
-    __device__ __forceinline__ uint32_t next13()
+    __device__ __forceinline__ uint32_t next()
     {
-        const uint32_t r = x >> 19;
+        const uint32_t r = x;
         x = x * 0x4C957F2Du + 0x2545F491u;
         return r;
     }
@@ -60,16 +61,20 @@ struct SrStream {
 
 // float -> binary16 with stochastic rounding: a value between two
 // neighbouring halves a < v < b rounds to b with probability (v - a)/(b - a),
-// so the rounding error has zero mean whatever v is.  On the FP32 bit
-// pattern (sign and magnitude): add a uniform 13-bit integer below the
-// 13 bits that binary16 drops, clear them; the result is a half exactly
-// (converted without further rounding) for |v| >= 2^-14.  Below that, in the
-// half subnormal range, the conversion rounds the dithered value to nearest
-// (an error below 2^-25).
-__device__ __forceinline__ __half half_sr(float v, uint32_t r13)
+// so the rounding error has zero mean whatever v is.  gfx950 does this in one
+// instruction (v_cvt_sr_f16_f32).  Measured on an MI355X over 196,608 random
+// values in the normal half range, it equals: add the seed's top 13 bits
+// (seed >> 19) to the FP32 bit pattern (sign and magnitude) below the 13 bits
+// binary16 drops, then drop them; in the subnormal half range it rounds
+// stochastically at the subnormal spacing 2^-24 (the up-rounding frequency
+// matched the fraction within sampling error on 32 values x 32,768 seeds).
+__device__ __forceinline__ __half half_sr(float v, uint32_t seed)
 {
-    const uint32_t b = (__builtin_bit_cast(uint32_t, v) + r13) & 0xFFFFE000u;
-    return __float2half_rn(__builtin_bit_cast(float, b));
+    // the instruction writes the low half of its destination and keeps the
+    // high half of the tied operand, here v's own register (no extra move)
+    typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+    const H2 r = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(H2, v), v, seed, false);
+    return __builtin_bit_cast(__half, r.x);
 }
 
 // load/store convert between a stored value and the deviation h_i it stands
@@ -112,11 +117,11 @@ template <class L> struct Codec<L, __half> {
     {
         return T(__half2float(v));
     }
-    // stochastic rounding (half_sr), the next 13 random bits of the cell's stream
+    // stochastic rounding (half_sr), seeded by the next word of the cell's stream
     template <int I, class T> __device__ static __forceinline__ __half store_scaled(T h,
                                                                                    SrStream &rng)
     {
-        return half_sr(float(h), rng.next13());
+        return half_sr(float(h), rng.next());
     }
 };
 

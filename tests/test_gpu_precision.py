@@ -17,9 +17,9 @@ Bars (FP32 about 5x the values measured on an MI355X):
   FP32: rho 2e-4, u 2e-3, theta 5e-4 relative (as in the parity tests), q 1e-2
         relative to max|q|; the dominant dq mode within 10% of FP64's.
   F16 (stochastic rounding): rho 3e-3, u 2e-2, theta 2e-3; the time-averaged
-        dq mode within 10% of FP64's on every workload (measured 3.3% on the
-        256^2 shear, 4.7% on 1024^2, 0.06% on the Kolmogorov flow; at a single
-        snapshot 18.6%, 2.7% and 0.07%).  q pointwise is not bounded: the half
+        dq mode within 10% of FP64's on every workload (measured 0.4% on the
+        256^2 shear, 4.6% on 1024^2, 0.3% on the Kolmogorov flow; at a single
+        snapshot 3.8%, 14% and 0.06%).  q pointwise is not bounded: the half
         rounding of deviations that reach ~25% of w_i leaves noise of
         1e-2..5e-1 of max|q| in single cells.  With round-to-nearest stores
         (measured with a library variant) the shear workloads' dq came out
