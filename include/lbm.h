@@ -189,6 +189,22 @@ LBM_API lbm_status lbm_totals_device(lbm_sim *s, double *out_dev);
  * step (the quantity q_err of Sec. 2 refers to).  q: D*N device doubles. */
 LBM_API lbm_status lbm_heat_flux(lbm_sim *s, double *q);
 
+/* The rounding the step applies when it stores F16 deviations
+ * (LBM_F16DEV): each of n FP32 values v[k] becomes a binary16 out[k] (bit
+ * pattern) by stochastic rounding -- a value between neighbouring halves
+ * a < v < b becomes b with probability (v - a)/(b - a), so the rounding error
+ * has zero mean -- with seed[k] as its random bits.  In the normal half range
+ * the result is: add seed[k] >> 19 to the FP32 bit pattern (sign and
+ * magnitude) below the 13 bits binary16 drops, then drop them; below 2^-14 the
+ * rounding is stochastic at the subnormal spacing 2^-24.  Values a half holds
+ * exactly are returned unchanged.  v, seed and out are device arrays of n
+ * elements (out may not overlap the inputs); the call is enqueued on
+ * hip_stream (NULL: the null stream) and not waited for.  For callers that
+ * encode F16 deviations themselves, and for tests of the rounding.
+ * LBM_EINVAL if n < 0, or n > 0 with a NULL pointer; n = 0 does nothing. */
+LBM_API lbm_status lbm_round_f16_stochastic(const float *v, const uint32_t *seed, uint16_t *out,
+                                            int64_t n, void *hip_stream);
+
 /* Access-pattern diagnostic: `repeats` passes of the memory traffic of the
  * step alone -- the streaming of eq. (lbm): every population read from its
  * pull source x - c_i and written back unchanged at the cell's own slot of

@@ -31,6 +31,7 @@ NOALLOC_MAX_SIMS = 256  # LBM_NOALLOC_MAX_SIMS
 API_SYMBOLS = (
     "lbm_workspace_bytes", "lbm_create", "lbm_set_force", "lbm_step", "lbm_moments",
     "lbm_destroy", "lbm_last_error", "lbm_totals", "lbm_totals_device", "lbm_heat_flux", "lbm_pattern_pass",
+    "lbm_round_f16_stochastic",
     "lbm_population_bytes",
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
     "lbm_set_stream", "lbm_set_block", "lbm_set_resident_limit", "lbm_set_viscosity",
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
     L.lbm_totals_device.argtypes = [_vp, _vp]
     L.lbm_totals_device.restype = _i32
     L.lbm_heat_flux.argtypes = [_vp, _vp]
+    L.lbm_round_f16_stochastic.argtypes = [_vp, _vp, _vp, _i64, _vp]
+    L.lbm_round_f16_stochastic.restype = _i32
     L.lbm_heat_flux.restype = _i32
     L.lbm_pattern_pass.argtypes = [_vp, _i64]
     L.lbm_pattern_pass.restype = _i32

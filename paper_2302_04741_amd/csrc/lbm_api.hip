@@ -459,6 +459,17 @@ lbm_status lbm_totals_device(lbm_sim *s, double *out_dev)
     return ok();
 }
 
+lbm_status lbm_round_f16_stochastic(const float *v, const uint32_t *seed, uint16_t *out,
+                                    int64_t n, void *hip_stream)
+{
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!v || !seed || !out) return fail(LBM_EINVAL, "v, seed and out must not be NULL");
+    hipError_t e = launch_round_f16_sr(v, seed, out, n, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return dev_fail(e, "rounding kernel launch");
+    return ok();
+}
+
 lbm_status lbm_heat_flux(lbm_sim *s, double *q)
 {
     if (!s) return fail(LBM_EINVAL, "handle is NULL");
@@ -619,7 +630,7 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.5.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.6.0"; }
 
 // ---------------------------------------------------------------------------
 // batches

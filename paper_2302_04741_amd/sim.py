@@ -410,3 +410,26 @@ def batch_step_noalloc(sims, n: int = 1, stream=None):
                                         ctypes.c_void_p(stream.cuda_stream)))
     for st in others.values():
         st.wait_stream(stream)
+
+
+def round_f16_stochastic(v, seed, stream=None):
+    """The F16 storage's stochastic rounding (lbm_round_f16_stochastic) of a
+    float32 CUDA tensor `v` with the uint32 random words `seed` (an int32 or
+    uint32 CUDA tensor of the same size); returns the binary16 results as a
+    float16 tensor of v's shape, enqueued on `stream` (default: the current
+    stream)."""
+    torch = _torch()
+    if v.dtype != torch.float32 or not v.is_cuda:
+        raise TypeError("v must be a float32 CUDA tensor")
+    if seed.dtype not in (torch.int32, torch.uint32) or seed.device != v.device:
+        raise TypeError("seed must be an int32/uint32 tensor on v's device")
+    if seed.numel() != v.numel():
+        raise ValueError("seed and v differ in size")
+    v, seed = v.contiguous(), seed.contiguous()
+    out = torch.empty(v.shape, dtype=torch.float16, device=v.device)
+    stream = stream if stream is not None else torch.cuda.current_stream(v.device)
+    check(load().lbm_round_f16_stochastic(ctypes.c_void_p(v.data_ptr()),
+                                          ctypes.c_void_p(seed.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), int(v.numel()),
+                                          ctypes.c_void_p(stream.cuda_stream)))
+    return out

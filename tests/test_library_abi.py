@@ -270,3 +270,14 @@ def test_batch_step_noalloc_argument_checks(lib):
     assert step(arr, 1, -1, None) == _lib.LBM_EINVAL
     assert step(arr, 1, 1, None) == _lib.LBM_EINVAL  # a NULL member
     assert "NULL" in lib.lbm_last_error().decode()
+
+
+def test_round_f16_stochastic_argument_checks(lib):
+    """Argument errors of the rounding entry point are found before any HIP
+    call; n = 0 does nothing, whatever the pointers."""
+    rnd = lib.lbm_round_f16_stochastic
+    assert rnd(None, None, None, 0, None) == _lib.LBM_OK
+    assert rnd(None, None, None, -1, None) == _lib.LBM_EINVAL
+    assert ">= 0" in lib.lbm_last_error().decode()
+    assert rnd(None, None, None, 5, None) == _lib.LBM_EINVAL
+    assert "NULL" in lib.lbm_last_error().decode()
