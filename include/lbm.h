@@ -68,10 +68,11 @@ typedef enum { LBM_D2Q37 = 0, LBM_D3Q39 = 1 } lbm_lattice;
  * (see lbm_params.rho0); LBM_F16DEV stores h_i scaled by 2^k_i, k_i =
  * round(-log2 w_i), as IEEE half, so that deviations stay normal numbers.
  * The step stores LBM_F16DEV values with stochastic rounding (up or down with
- * probabilities that make the rounding error zero-mean), its random bits a
- * hash of (cell, population, step number): deterministic, and independent of
- * launch shape, batching and the other members; the initial state rounds to
- * nearest. */
+ * probabilities that make the rounding error zero-mean; lbm_round_f16_stochastic
+ * applies the same rounding to plain arrays), its random bits drawn from a
+ * hash of (cell, step number) walked once per population: deterministic, and
+ * independent of launch shape, batching and the other members; the initial
+ * state rounds to nearest. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
 
 /* Truncation of the force expansion eq. (F).  The paper's N = 0, 1, 2 are
