@@ -259,6 +259,12 @@ hipError_t launch_steps(const lbm_sim *s, int &cur, int64_t nsteps, int64_t &don
 
 }  // namespace
 
+namespace lbm {
+// F16 stochastic rounding of plain arrays (defined with the F16 field kernels)
+hipError_t launch_round_f16_sr(const float *v, const uint32_t *seed, uint16_t *out, int64_t n,
+                                hipStream_t stream);
+}  // namespace lbm
+
 extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_params *p)

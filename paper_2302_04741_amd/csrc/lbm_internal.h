@@ -591,8 +591,6 @@ hipError_t launch_moments(int lat, int storage, const void *A, double *rho, doub
 hipError_t launch_heat_flux(int lat, int storage, int eq, int fo, const void *A, double *q,
                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
                             const LaunchCfg &lc);
-hipError_t launch_round_f16_sr(const float *v, const uint32_t *seed, uint16_t *out, int64_t n,
-                                hipStream_t stream);
 hipError_t launch_totals(int lat, int storage, const void *A, double *partials, double *out_dev,
                          const GridDims &gd, const StepCoef &co, hipStream_t stream);
 hipError_t launch_convert(int storage, const double *src, void *dst, int64_t n,
