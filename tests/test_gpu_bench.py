@@ -77,10 +77,10 @@ def test_bench_line_d2q37():
 
 @pytest.mark.parametrize("storage,floor", [("f32", 0.90), ("f16dev", 0.85)])
 def test_step_stays_near_its_pattern_ceiling(storage, floor):
-    """Performance guard, relative to the same box: the fused step on the
+    """Performance guard, relative to the same machine: the fused step on the
     256^3 benchmark grid moves its bytes at least `floor` times as fast as its
     own loads and stores do without the arithmetic (best block size), so a
-    change that slows the kernel fails here whatever the box's absolute speed.
+    change that slows the kernel fails here whatever the machine's absolute speed.
     Measured: FP32 1.02-1.03, F16 0.94-0.98."""
     import torch
 
