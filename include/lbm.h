@@ -242,15 +242,6 @@ LBM_API lbm_status lbm_set_stream(lbm_sim *s, void *hip_stream);
  * wavefronts).  Results do not depend on it. */
 LBM_API lbm_status lbm_set_block(lbm_sim *s, int32_t threads);
 
-/* Small grids: a handle with at most max_cells cells steps (eq. (lbm), the same
- * arithmetic) in a single-workgroup kernel that runs many steps per launch (a workgroup barrier between steps)
- * instead of one launch per step.  Off by default (0): one
- * compute unit doing every cell costs about as much per step as a launch over
- * the whole chip, so it pays only on the smallest grids (a few hundred cells).
- * Results differ from the one-launch-per-step kernels by rounding at most (the
- * same arithmetic, compiled into a different kernel).  LBM_EINVAL if negative. */
-LBM_API lbm_status lbm_set_resident_limit(lbm_sim *s, int64_t max_cells);
-
 /* Relaxation time per cell (Sec. 3 of the paper: tau = mu/(rho theta) keeps the
  * dynamic viscosity mu and the heat conductivity constant).  mu > 0: every
  * step, the stress and the heat flux use tau^ = mu/(rho theta) + 1/2 with the

@@ -34,7 +34,7 @@ API_SYMBOLS = (
     "lbm_round_f16_stochastic",
     "lbm_population_bytes",
     "lbm_get_populations", "lbm_set_populations", "lbm_step_count", "lbm_set_step_count",
-    "lbm_set_stream", "lbm_set_block", "lbm_set_resident_limit", "lbm_set_viscosity",
+    "lbm_set_stream", "lbm_set_block", "lbm_set_viscosity",
     "lbm_set_walls", "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set",
     "lbm_batch_step", "lbm_batch_set_launch", "lbm_batch_destroy", "lbm_batch_step_noalloc",
     "lbm_graph_create", "lbm_graph_launch", "lbm_graph_destroy", "lbm_lattice_table",
@@ -120,8 +120,6 @@ def load() -> ctypes.CDLL:
     L.lbm_set_stream.restype = _i32
     L.lbm_set_block.argtypes = [_vp, _i32]
     L.lbm_set_block.restype = _i32
-    L.lbm_set_resident_limit.argtypes = [_vp, _i64]
-    L.lbm_set_resident_limit.restype = _i32
     L.lbm_set_viscosity.argtypes = [_vp, ctypes.c_double]
     L.lbm_set_viscosity.restype = _i32
     _d = ctypes.c_double

@@ -41,9 +41,8 @@ struct lbm_sim {
     int64_t step;
     int block;
     int64_t gen;  // bumped when launch arguments change (force, block, stream, viscosity,
-                  // plates, resident limit): batches and graphs built before are stale
+                  // plates): batches and graphs built before are stale
     WallDesc wd;  // plates (off unless lbm_set_walls)
-    int64_t resident_max;  // grids of at most this many cells step in one workgroup
     double *wall_part;     // plates: partial sums of the crossing slots, per buffer
     double *wall_e;        // plates: emission tables
     bool wall_fresh;       // plates: wall_part holds the sums of the current state
@@ -192,12 +191,6 @@ LaunchCfg cfg(const lbm_sim *s, int cur)
 }
 LaunchCfg cfg(const lbm_sim *s) { return cfg(s, s->cur); }
 
-// The resident kernel is opt-in (lbm_set_resident_limit): one CU computing
-// every cell costs about as much per step as a launch over the whole chip, so
-// it gains little (at most ~15%, grids below ~300 cells) and loses above.
-constexpr int64_t RESIDENT_DEFAULT_MAX_CELLS = 0;
-constexpr int64_t RESIDENT_MAX_STEPS_PER_LAUNCH = 4096;
-
 // With plates, whatever reads the state needs the partial sums of the current
 // state: steps keep them (each writes those of the state it produces); after
 // the state was written otherwise (initialisation, lbm_set_populations) one
@@ -212,8 +205,6 @@ hipError_t wall_densities(lbm_sim *s, hipStream_t stream)
     return e;
 }
 hipError_t wall_densities(lbm_sim *s) { return wall_densities(s, s->stream); }
-
-bool resident(const lbm_sim *s) { return s->N <= s->resident_max; }
 
 // One time step, one launch: K1, or with plates K1c (which also writes the
 // partial sums of the state it produces).
@@ -230,24 +221,11 @@ hipError_t launch_one_step(const lbm_sim *s, int cur)
 
 // Enqueues nsteps steps of the state held in pop[cur] (with plates, its partial
 // sums must be current); on return cur names the buffer holding the advanced
-// state and done the steps enqueued (all of them unless a launch failed).
-// Grids within the resident limit take the resident kernel, many steps per
-// launch in chunks that keep every launch short; the others one launch per step.
+// state and done the steps enqueued (all of them unless a launch failed), one
+// launch per step.
 hipError_t launch_steps(const lbm_sim *s, int &cur, int64_t nsteps, int64_t &done)
 {
     done = 0;
-    if (resident(s)) {
-        while (done < nsteps) {
-            const int k = int(std::min<int64_t>(nsteps - done, RESIDENT_MAX_STEPS_PER_LAUNCH));
-            hipError_t e = launch_resident(s->p.lattice, s->p.storage, s->eq, s->p.force_order,
-                                           s->pop[cur], s->pop[cur ^ 1], s->gd, s->fd, s->co,
-                                           cfg(s, cur), k);
-            if (e != hipSuccess) return e;
-            cur ^= (k & 1);
-            done += k;
-        }
-        return hipSuccess;
-    }
     while (done < nsteps) {
         hipError_t e = launch_one_step(s, cur);
         if (e != hipSuccess) return e;
@@ -322,7 +300,6 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t workspace_byt
     }
     s->step = 0;
     s->block = 0;
-    s->resident_max = RESIDENT_DEFAULT_MAX_CELLS;
     hipError_t e = launch_init(p->lattice, p->storage, s->eq, p->force_order, rho, u, theta,
                                s->pop[0], s->gd, s->fd, s->co, cfg(s));
     if (e == hipSuccess) e = set_step_number(s);
@@ -575,15 +552,6 @@ lbm_status lbm_set_viscosity(lbm_sim *s, double mu)
     return ok();
 }
 
-lbm_status lbm_set_resident_limit(lbm_sim *s, int64_t max_cells)
-{
-    if (!s) return fail(LBM_EINVAL, "handle is NULL");
-    if (max_cells < 0) return fail(LBM_EINVAL, "max_cells must be >= 0");
-    s->resident_max = max_cells;
-    s->gen++;
-    return ok();
-}
-
 lbm_status lbm_set_walls(lbm_sim *s, int32_t enable, double theta_b, double theta_t, double u_b,
                          double u_t)
 {
@@ -636,7 +604,7 @@ int32_t lbm_lattice_table(int32_t lattice, int32_t *c, double *w, double *r)
     return Q;
 }
 
-const char *lbm_version(void) { return "lbm-gfx950 0.6.0"; }
+const char *lbm_version(void) { return "lbm-gfx950 0.7.0"; }
 
 // ---------------------------------------------------------------------------
 // batches

@@ -69,21 +69,6 @@ hipError_t launch_wall_step(int lat, int storage, int eq, int fo, const void *A,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_resident(int lat, int storage, int eq, int fo, void *A, void *B,
-                           const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                           const LaunchCfg &lc, int nsteps)
-{
-#define LBM_RS(L, S) return launch_resident_ls<L, S>(eq, fo, A, B, gd, fd, co, lc, nsteps)
-    if (lat == 0 && storage == 0) LBM_RS(0, double);
-    if (lat == 0 && storage == 1) LBM_RS(0, float);
-    if (lat == 0 && storage == 2) LBM_RS(0, __half);
-    if (lat == 1 && storage == 0) LBM_RS(1, double);
-    if (lat == 1 && storage == 1) LBM_RS(1, float);
-    if (lat == 1 && storage == 2) LBM_RS(1, __half);
-#undef LBM_RS
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_multi_step(int lat, int storage, int eq, int fo, const BatchLaunch &bl)
 {
 #define LBM_MS(L, S) return launch_multi_step_ls<L, S>(eq, fo, bl)

@@ -617,10 +617,6 @@ hipError_t launch_wall_mass(int lat, int storage, const void *A, const GridDims 
 hipError_t launch_wall_step(int lat, int storage, int eq, int fo, const void *A, void *B,
                             const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
                             const LaunchCfg &lc);
-// small grids: nsteps steps in one single-workgroup launch, A -> B -> A ...
-hipError_t launch_resident(int lat, int storage, int eq, int fo, void *A, void *B,
-                           const GridDims &gd, const ForceDesc &fd, const StepCoef &co,
-                           const LaunchCfg &lc, int nsteps);
 
 // Per-lattice / per-storage pieces, each explicitly instantiated in its own
 // translation unit (step_*.hip, aux_*.hip) so that the build parallelises.
@@ -634,10 +630,6 @@ hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const Gri
                                const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc);
 template <int LAT, class S>
 hipError_t launch_pattern_ls(const void *A, void *B, const GridDims &gd, const LaunchCfg &lc);
-template <int LAT, class S>
-hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &gd,
-                              const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc,
-                              int nsteps);
 template <int LAT>
 hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, int64_t ny,
                                double *e, hipStream_t stream);

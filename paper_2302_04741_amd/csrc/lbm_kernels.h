@@ -147,14 +147,13 @@ __device__ __forceinline__ double wall_emitted(const WallDesc &wd, const GridDim
     return rw * wd.e[side * (L::Q + 1) + i] - w * rho0;
 }
 
-template <class L, class S, class T, bool WALLS = false, bool LANE_ROWS = false>
+template <class L, class S, class T, bool WALLS = false>
 __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &gd, int x, int y,
                                        int z, T (&h)[L::Q], const WallDesc *wd = nullptr,
                                        double rho0 = 0.0)
 {
     // x offsets are per lane (7 distinct byte offsets); y and z are uniform over
-    // the wavefront, so each row offset and each plane resource is a scalar
-    // (LANE_ROWS: y and z vary per lane and the row offset joins the lane offset).
+    // the wavefront, so each row offset and each plane resource is a scalar.
     uint32_t xs[7];
     int ys[7], zs[7];
 #pragma unroll
@@ -180,11 +179,7 @@ __device__ __forceinline__ void gather(const S *__restrict__ A, const GridDims &
         const uint32_t row =
             uint32_t((int64_t(zs[cz + 3]) * gd.ny + ys[cy + 3]) * gd.px) * uint32_t(sizeof(S));
         const auto r = plane_rsrc(A + int64_t(i) * P, plane_bytes);
-        if constexpr (LANE_ROWS)
-            h[i] = Codec<L, S>::template load_scaled<i, T>(
-                BufIO<S>::load(r, xs[cx + 3] + row, 0u));
-        else
-            h[i] = Codec<L, S>::template load_scaled<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
+        h[i] = Codec<L, S>::template load_scaled<i, T>(BufIO<S>::load(r, xs[cx + 3], row));
     });
 }
 
@@ -213,7 +208,7 @@ template <int LAT, class S> inline int step_default_threads(int64_t waves)
 // force, relaxation, store.  y and z must be uniform over the wavefront.
 // `step` is the step number (the state read is after `step` steps): with F16
 // storage it keys the stochastic rounding of every value stored.
-template <int LAT, class S, int EQ, int FO, bool WALLS = false, bool LANE_ROWS = false>
+template <int LAT, class S, int EQ, int FO, bool WALLS = false>
 __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict__ B,
                                           const GridDims &gd, const ForceDesc &fd,
                                           const StepCoef &co, int x, int y, int z,
@@ -234,7 +229,7 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     using C = Codec<L, S>;
     SrStream rng{C::STOCHASTIC ? sr_key(uint32_t(cell), step) : 0u};
     T h[L::Q];
-    gather<L, S, T, WALLS, LANE_ROWS>(A, gd, x, y, z, h, wd, co.rho0);
+    gather<L, S, T, WALLS>(A, gd, x, y, z, h, wd, co.rho0);
     T g[3];
     load_force<T, T, L::D>(fd, gd, x, y, z, cell, g);
 
@@ -248,9 +243,8 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     // every term is a small deviation, so the rounding stays at the size of h.
     const T om = cs.om;
     const T drho = cs.drho;
-    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S)) +
-                        (LANE_ROWS ? uint32_t(rowbase) * uint32_t(sizeof(S)) : 0u);
-    const uint32_t ro = LANE_ROWS ? 0u : uint32_t(rowbase) * uint32_t(sizeof(S));
+    const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
+    const uint32_t ro = uint32_t(rowbase) * uint32_t(sizeof(S));
     const uint32_t plane_bytes = uint32_t(P * int64_t(sizeof(S)));
     // with plates: the partial sums of the state written here (the slots whose
     // next move crosses a plate, as stored), for the next step's emission
@@ -724,55 +718,6 @@ __global__ void __launch_bounds__(256)
     const int64_t ncol = int64_t(gd.nx) * gd.nz;
     const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (col < ncol) wall_column_density<Lattice<LAT>, S>(A, gd, co, wd, col);
-}
-
-// ---------------------------------------------------------------------------
-// K1d: resident multi-step kernel for small grids.  One workgroup runs nsteps
-// steps in one launch, the two buffers alternating, with a workgroup barrier
-// between steps (a barrier makes the global writes before it visible to the
-// whole workgroup after it).  Each lane takes cells of the flattened grid
-// (64 consecutive cells per wavefront, across row ends), so rows vary per lane
-// and their offsets join the lane offsets.  With plates every cell takes the
-// plates' emission in place of the sources behind them (densities from the
-// partial sums the previous step wrote) and writes its row's partial sums.
-// Every cell is updated by one thread with the arithmetic of the single-grid
-// step.
-// ---------------------------------------------------------------------------
-// Largest workgroup of the resident kernel whose registers fit without
-// spilling: with plates a wavefront needs more than half the register file of
-// a SIMD (one wavefront per SIMD), without them at most half (FP64) or a
-// quarter (FP32 arithmetic).
-template <class S, bool WALLS>
-constexpr int resident_max_threads()
-{
-    return WALLS ? 256 : (sizeof(S) == 8 ? 512 : 1024);
-}
-
-template <int LAT, class S, int EQ, int FO, bool WALLS>
-__global__ void __launch_bounds__((resident_max_threads<S, WALLS>()))
-    resident_kernel(S *__restrict__ P0, S *__restrict__ P1, GridDims gd, ForceDesc fd,
-                    StepCoef co, WallDesc wd, int nsteps, uint32_t *ctr, int cur)
-{
-    const int64_t N = gd.N;
-    WallDesc w = wd;
-    const uint32_t step0 = step_number<S>(ctr, cur);
-    for (int n = 0; n < nsteps; ++n) {
-        const S *A = (n & 1) ? P1 : P0;
-        S *B = (n & 1) ? P0 : P1;
-        w.par = wd.par ^ (n & 1);  // the partial sums of A; the step writes B's
-        for (int64_t c = threadIdx.x; c < N; c += blockDim.x) {
-            const int x = int(c % gd.nx);
-            const int64_t row = c / gd.nx;
-            const int y = int(row % gd.ny), z = int(row / gd.ny);
-            step_cell<LAT, S, EQ, FO, WALLS, true>(A, B, gd, fd, co, x, y, z,
-                                                   step0 + uint32_t(n), &w);
-        }
-        __syncthreads();
-    }
-    // every lane read the counter before the first barrier: the last step's
-    // successor slot can be written now
-    advance_step_number<S>(ctr, cur ^ ((nsteps - 1) & 1), step0 + uint32_t(nsteps - 1),
-                           threadIdx.x == 0 && nsteps > 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -145,32 +145,6 @@ hipError_t launch_wall_step_ls(int eq, int fo, const void *A, void *B, const Gri
     });
 }
 
-template <int LAT, class S>
-hipError_t launch_resident_ls(int eq, int fo, void *A, void *B, const GridDims &gd,
-                              const ForceDesc &fd, const StepCoef &co, const LaunchCfg &lc,
-                              int nsteps)
-{
-    // one workgroup: a lane per cell up to the variant's register limit
-    auto threads = [&](int cap) {
-        const int bx = lc.block > 0 ? std::min(lc.block, cap) : cap;
-        return int(std::min<int64_t>(bx, (gd.N + 63) / 64 * 64));
-    };
-    return with_eq_fo<LAT>(eq, fo, [&](auto E, auto O) {
-        constexpr int EQ = decltype(E)::value, FO = decltype(O)::value;
-        if (lc.walls.on)
-            hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, true>), dim3(1),
-                               dim3(threads(resident_max_threads<S, true>())), 0, lc.stream,
-                               static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
-                               nsteps, lc.ctr, lc.cur);
-        else
-            hipLaunchKernelGGL((resident_kernel<LAT, S, EQ, FO, false>), dim3(1),
-                               dim3(threads(resident_max_threads<S, false>())), 0, lc.stream,
-                               static_cast<S *>(A), static_cast<S *>(B), gd, fd, co, lc.walls,
-                               nsteps, lc.ctr, lc.cur);
-        return hipGetLastError();
-    });
-}
-
 template <int LAT>
 hipError_t launch_wall_setup_l(int eq, const double *theta, const double *uw, int64_t ny,
                                double *e, hipStream_t stream)

@@ -244,11 +244,6 @@ class Sim:
         step's access pattern."""
         check(load().lbm_pattern_pass(self.handle, int(repeats)))
 
-    def set_resident_limit(self, max_cells: int):
-        """Grids of at most max_cells cells step many steps per launch in one
-        workgroup (default 0: always one launch per step)."""
-        check(load().lbm_set_resident_limit(self.handle, int(max_cells)))
-
     def set_viscosity(self, mu: float):
         """mu > 0: per-cell relaxation time tau^ = mu/(rho theta) + 1/2 (the
         dynamic viscosity held constant); 0: the constant tau_hat again."""

@@ -131,9 +131,9 @@ def test_plate_argument_checks(sim_mod):
 def test_restored_state_with_plates(sim_mod):
     """A state written from outside (lbm_set_populations) gets the plates' row sums
     of that state before the next step, on every path: direct steps, a graph
-    captured before the restore, and the resident kernel.  They are recomputed by
-    the column pass instead of taken from the producing step, so the runs agree
-    with the uninterrupted one to rounding."""
+    captured before the restore, and a batch.  They are recomputed by the column
+    pass instead of taken from the producing step, so the runs agree with the
+    uninterrupted one to rounding."""
     wl = channel("D2Q37", (8, 20, 1), seed=4, mu=0.1)
     stream = torch.cuda.Stream()
     a = sim_mod.from_workload(wl, stream=stream)
@@ -149,12 +149,14 @@ def test_restored_state_with_plates(sim_mod):
     c.set_populations(snap)
     c.step(50)
     d = sim_mod.from_workload(wl, stream=stream)
-    d.set_resident_limit(1 << 40)
     d.set_populations(snap)
-    d.step(50)
+    bt = sim_mod.Batch(1, stream=stream)
+    bt.set([d])
+    bt.step(50)
     for s in (b, c, d):
         errs = rel_err(gpu_moments(s), ref)
         assert max(errs) < 1e-13, errs
+    bt.close()
     g.close()
 
 
