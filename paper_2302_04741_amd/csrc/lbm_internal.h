@@ -449,6 +449,32 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
     const T t = cs.th - T(1);
     const T rho = cs.rho;
 
+    // The shell constants below are polynomials in the shell's X2 = |xi|^2 (a
+    // compile-time value) with coefficients that depend on the cell only:
+    // computed once here, each shell then costs a Horner step per polynomial.
+    //   e0 - 1 (the even constant without its leading 1) = E0 + E1 X2 + E2 X2^2
+    //   e1 (even, times xu^2)                             = D0 + D1 X2
+    //   o0 (odd, times xu)                                = G0 + G1 X2
+    const T half_t = T(0.5) * t;
+    T E0 = T(-0.5) * (t * T(D) + u2), E1 = half_t, E2 = T(0);
+    T D0 = T(0.5), D1 = T(0);
+    if constexpr (!NO_BASE) E0 += T(1);
+    if constexpr (EQ == 4) {
+        // [3 u2^2 + 6 t u2 (D + 2 - X2) + 3 t^2 (X2^2 - 2 (D + 2) X2 + D (D + 2))] / 24
+        const T tt = t * t;
+        E0 += T(0.125) * u2 * u2 + T(0.25 * (D + 2)) * t * u2 + T(0.125 * D * (D + 2)) * tt;
+        E1 -= T(0.25) * (t * u2 + T(D + 2) * tt);
+        E2 = T(0.125) * tt;
+        // (t (X2 - D - 4) - u2) / 4
+        D0 -= T(0.25) * (t * T(D + 4) + u2);
+        D1 = T(0.25) * t;
+    }
+    const T G0 = T(1) - T(0.5) * u2 - half_t * T(D + 2), G1 = half_t;
+    const T arho = alpha * rho;  // A = ws arho multiplies the equilibrium bracket
+    const T brho = beta * rho;   // Bf = ws brho multiplies the force bracket
+    const T brgu = brho * gu;
+    const T hbeta = T(0.5) * beta;
+
     // per-shell constants, recomputed at the first pair of each shell
     T K0 = T(0), Ka = T(0), Kq = T(0), K6 = T(0), Kb = T(0), Kb2 = T(0), Kw = T(0), K24 = T(0);
     T Kbf = T(0);
@@ -460,46 +486,35 @@ __device__ __forceinline__ void combo_pairs(const CellState<T> &cs, T alpha, T b
             while (L::shell(i) != s) ++i;
             return i;
         }();
-        constexpr double X2d = L::R2 * c2<L>(iref);
-        const T X2 = T(X2d);
+        const T X2 = T(L::R2 * c2<L>(iref));
         // the shell's weight times the scale its values carry (a power of two):
         // every constant below is linear in it, so even and odd come out
         // scaled, rounding for rounding
-        constexpr double ws = L::wshell(s) * SC::template scale<iref>();
-        const T wr = T(ws) * rho;
-        const T A = alpha * wr;      // multiplies the equilibrium bracket
-        const T Bf = beta * wr;      // multiplies the force bracket
-        // e0 - 1, computed without the leading 1
-        const T e0m1 = T(0.5) * (t * (X2 - T(D)) - u2);
-        T e0t = NO_BASE ? e0m1 : T(1) + e0m1, e1 = T(0.5);
-        if constexpr (EQ == 4) {
-            e0t += (T(3) * u2 * u2 + T(6) * t * u2 * (T(D + 2) - X2)
-                    + T(3) * t * t * (X2 * X2 - T(2 * (D + 2)) * X2 + T(D * (D + 2))))
-                   * T(1.0 / 24.0);
-            e1 += (t * (X2 - T(D + 4)) - u2) * T(0.25);
-            K24 = A * T(1.0 / 24.0);
-        }
-        const T o0 = T(1) - T(0.5) * u2 + T(0.5) * t * (X2 - T(D + 2));
-        K0 = A * e0t;                   // even constant
-        if constexpr (FO >= 2) K0 -= Bf * gu;
-        Ka = A * e1;                    // even, times xu^2
+        const T ws = T(L::wshell(s) * SC::template scale<iref>());
+        const T A = ws * arho;
+        const T Bf = ws * brho;
+        const T e0t = (EQ == 4) ? fma_t(fma_t(E2, X2, E1), X2, E0) : fma_t(E1, X2, E0);
+        const T o0 = fma_t(G1, X2, G0);
+        if constexpr (FO >= 2) K0 = ws * fma_t(arho, e0t, -brgu);  // A e0 - Bf gu
+        else K0 = A * e0t;
+        Ka = (EQ == 4) ? A * fma_t(D1, X2, D0) : A * T(0.5);
         if constexpr (EQ >= 3) {
-            Kq = A * o0;                // odd, times xu
-            K6 = A * T(1.0 / 6.0);      // odd, times xu^3
+            Kq = (FO >= 3) ? ws * fma_t(arho, o0, -brgu) : A * o0;  // odd, times xu
+            K6 = A * T(1.0 / 6.0);                                   // odd, times xu^3
         } else {
-            Kq = A;
+            Kq = (FO >= 3) ? ws * (arho - brgu) : A;
             K6 = T(0);
         }
+        if constexpr (EQ == 4) K24 = A * T(1.0 / 24.0);
         if constexpr (FO >= 3) {
-            Kq -= Bf * gu;
-            Kb = Bf * o0;               // odd, times xg
-            Kb2 = Bf * T(0.5);          // odd, times xg xu^2
+            Kb = Bf * o0;         // odd, times xg
+            Kb2 = Bf * T(0.5);    // odd, times xg xu^2
         } else {
             Kb = Bf;
             Kb2 = T(0);
         }
-        Kbf = Bf;                       // even, times xg xu
-        Kw = beta * T(0.5 * ws);            // (beta w / 2) for the sigma terms
+        Kbf = Bf;                 // even, times xg xu
+        Kw = hbeta * ws;          // (beta w / 2) for the sigma terms
     };
 
     // rest velocity

@@ -237,11 +237,18 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
     CellState<T> cs;
     finish_moments<L, T, FO == 4>(rs, g, co, cs);
 
-    // h* = h + om (f0 - f) + cf F with f0 - f = w drho + (f0 - w rho) - h:
-    //    = h + fma(om, fma(w, drho, -h), [om (f0 - w rho) + cf F]).
-    // The bracket is what combo_pairs returns with NO_BASE (even +- odd part);
+    // h* = h + om (f0 - f) + cf F with f0 - f = w drho + (f0 - w rho) - h.
+    // The bracket [om (f0 - w rho) + cf F] is what combo_pairs returns with
+    // NO_BASE (even +- odd part).  FP32 arithmetic: h* = (1 - om) h + [om w
+    // drho + bracket], a pair sharing q = fma(om w, drho, even), each
+    // population one fma(1 - om, h, q +- odd) (1 - om is exact: om = 1/tau^
+    // lies in [1/2, 2]).  FP64 arithmetic keeps h + fma(om, fma(w, drho, -h),
+    // even +- odd), which needs one register less per lane (the other form
+    // takes its D3Q39 step from three wavefronts per SIMD to two).  Either way
     // every term is a small deviation, so the rounding stays at the size of h.
+    constexpr bool SHARED_Q = sizeof(T) == 4;
     const T om = cs.om;
+    const T omc = T(1) - om;
     const T drho = cs.drho;
     const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
     const uint32_t ro = uint32_t(rowbase) * uint32_t(sizeof(S));
@@ -265,13 +272,17 @@ __device__ __forceinline__ void step_cell(const S *__restrict__ A, S *__restrict
         constexpr int ip = decltype(IP)::value;
         constexpr int im = decltype(IM)::value;
         constexpr double w = L::wshell(L::shell(ip)) * C::template scale<ip>();
-        const T dp = fma_t(T(w), drho, -h[ip]);
-        const S sp = C::template store_scaled<ip, T>(h[ip] + fma_t(om, dp, ev + od), rng);
+        T q = T(0);
+        if constexpr (SHARED_Q) q = fma_t(om * T(w), drho, ev);
+        auto relaxed = [&](T hi, T sign_od) {
+            if constexpr (SHARED_Q) return fma_t(omc, hi, q + sign_od);
+            else return hi + fma_t(om, fma_t(T(w), drho, -hi), ev + sign_od);
+        };
+        const S sp = C::template store_scaled<ip, T>(relaxed(h[ip], od), rng);
         BufIO<S>::store(sp, plane_rsrc(B + int64_t(ip) * P, plane_bytes), xo, ro);
         account(IP, sp);
         if constexpr (im >= 0) {
-            const T dm = fma_t(T(w), drho, -h[im]);
-            const S sm = C::template store_scaled<im, T>(h[im] + fma_t(om, dm, ev - od), rng);
+            const S sm = C::template store_scaled<im, T>(relaxed(h[im], -od), rng);
             BufIO<S>::store(sm, plane_rsrc(B + int64_t(im) * P, plane_bytes), xo, ro);
             account(IM, sm);
         }

@@ -16,14 +16,21 @@ between snapshots; FP64 is averaged the same way).
 Bars (FP32 about 5x the values measured on an MI355X):
   FP32: rho 2e-4, u 2e-3, theta 5e-4 relative (as in the parity tests), q 1e-2
         relative to max|q|; the dominant dq mode within 10% of FP64's.
-  F16 (stochastic rounding): rho 3e-3, u 2e-2, theta 2e-3; the time-averaged
-        dq mode within 10% of FP64's on every workload (measured 0.4% on the
-        256^2 shear, 4.6% on 1024^2, 0.3% on the Kolmogorov flow; at a single
-        snapshot 3.8%, 14% and 0.06%).  q pointwise is not bounded: the half
-        rounding of deviations that reach ~25% of w_i leaves noise of
-        1e-2..5e-1 of max|q| in single cells.  With round-to-nearest stores
-        (measured with a library variant) the shear workloads' dq came out
-        37-217% off, twice with the wrong sign.
+  F16 (stochastic rounding): rho 3e-3, u 2e-2, theta 2e-3.  q pointwise is
+        not bounded: the half rounding of deviations that reach ~25% of w_i
+        leaves noise of 1e-2..5e-1 of max|q| in single cells.  The dq mode is
+        a sum of that noise over the grid, so its error is random: over
+        independent rounding realizations (the step counter that keys the
+        random bits offset by k * 10^6) its relative error, time-averaged as
+        above, had standard deviation 17% on the 256^2 shear (16 realizations,
+        mean +1.6%), 2.9% on 1024^2 (12, mean +0.6%) and 0.10% on the
+        Kolmogorov flow (8, mean +0.09%).  Asserted: a single run within 10% on
+        1024^2 and 256^3 (3.4 and 100 standard deviations); on 256^2 the mean
+        of 32 realizations within 10% (3.3 standard deviations of that mean),
+        their spread below 35%, and a single run within 70% (4 standard
+        deviations).  With round-to-nearest stores (measured with a library
+        variant) the shear workloads' dq came out 37-217% off, twice with the
+        wrong sign.
 """
 import math
 
@@ -50,11 +57,14 @@ def sim_mod():
 SNAPS, EVERY = 8, 25
 
 
-def run(sim_mod, wl, storage, force_order):
+def run(sim_mod, wl, storage, force_order, offset=0):
     """Moments and heat flux at STEPS, and the heat-flux modes averaged over
-    SNAPS snapshots EVERY steps apart from STEPS on."""
+    SNAPS snapshots EVERY steps apart from STEPS on.  offset: the step counter
+    starts there (F16: another realization of the stochastic rounding)."""
     wl.force_order = force_order
     s = sim_mod.from_workload(wl, storage=storage)
+    if offset:
+        s.step_count = offset
     s.step(STEPS)
     m = gpu_moments(s)
     q = to_host(s.heat_flux())
@@ -106,10 +116,14 @@ WORKLOADS = {
 }
 
 
-# bar on the time-averaged a3_F dq mode, relative to FP64
+# bar on the time-averaged a3_F dq mode of one run, relative to FP64 (F16 on
+# 256^2: four standard deviations of its rounding noise; the mean over
+# realizations is held to 10% by test_f16_dq_mean_over_realizations_shear256)
 TOL_DQ = {("f32", "shear256"): 0.10, ("f32", "shear1024"): 0.10, ("f32", "kolmogorov256"): 0.10,
-          ("f16dev", "shear256"): 0.10, ("f16dev", "shear1024"): 0.10,
+          ("f16dev", "shear256"): 0.70, ("f16dev", "shear1024"): 0.10,
           ("f16dev", "kolmogorov256"): 0.10}
+REALIZATIONS = 32
+OFFSET = 10 ** 6  # step-counter offset between realizations
 
 
 @pytest.fixture(scope="module")
@@ -148,3 +162,24 @@ def test_reduced_precision_errors(sim_mod, references, name, storage):
         assert eq <= TOL_Q32
         assert edq <= 0.10  # the a3_F correction is resolved at one snapshot
     assert edq_avg <= TOL_DQ[(storage, name)]  # and on the time average
+
+
+def test_f16_dq_mean_over_realizations_shear256(sim_mod, references):
+    """On the 256^2 shear one F16 run leaves the a3_F dq mode with a random
+    error of about 17% (one standard deviation): the rounding is unbiased, so
+    the mean over independent realizations converges to FP64's value."""
+    wl = WORKLOADS["shear256"]
+    ref_avg = references["shear256"][2]
+    ka = int(np.argmax(np.abs(ref_avg)))
+    vals = []
+    for k in range(REALIZATIONS):
+        _, _, a4 = run(sim_mod, wl(4), "f16dev", 4, offset=k * OFFSET)
+        _, _, a2 = run(sim_mod, wl(2), "f16dev", 2, offset=k * OFFSET)
+        vals.append((a2 - a4)[ka])
+    rel = (np.array(vals) - ref_avg[ka]) / abs(ref_avg[ka])
+    err_mean = abs(np.mean(vals) - ref_avg[ka]) / abs(ref_avg[ka])
+    print("shear256 f16dev, %d realizations: dq mode error mean %+.4f (of the mean %.4f), "
+          "std %.4f, max %.3f" % (REALIZATIONS, rel.mean(), err_mean, rel.std(ddof=1),
+                                  np.abs(rel).max()), flush=True)
+    assert err_mean <= 0.10
+    assert rel.std(ddof=1) <= 0.35
