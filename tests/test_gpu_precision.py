@@ -28,7 +28,8 @@ Bars (FP32 about 5x the values measured on an MI355X):
         1024^2 and 256^3 (3.4 and 100 standard deviations); on 256^2 the mean
         of 32 realizations within 10% (3.3 standard deviations of that mean),
         their spread below 35%, and a single run within 70% (4 standard
-        deviations).  With round-to-nearest stores (measured with a library
+        deviations); on 1024^2 also the mean of 12 realizations within 5% and
+        their spread below 8%.  With round-to-nearest stores (measured with a library
         variant) the shear workloads' dq came out 37-217% off, twice with the
         wrong sign.
 """
@@ -118,11 +119,10 @@ WORKLOADS = {
 
 # bar on the time-averaged a3_F dq mode of one run, relative to FP64 (F16 on
 # 256^2: four standard deviations of its rounding noise; the mean over
-# realizations is held to 10% by test_f16_dq_mean_over_realizations_shear256)
+# realizations is held to 10% by test_f16_dq_over_realizations)
 TOL_DQ = {("f32", "shear256"): 0.10, ("f32", "shear1024"): 0.10, ("f32", "kolmogorov256"): 0.10,
           ("f16dev", "shear256"): 0.70, ("f16dev", "shear1024"): 0.10,
           ("f16dev", "kolmogorov256"): 0.10}
-REALIZATIONS = 32
 OFFSET = 10 ** 6  # step-counter offset between realizations
 
 
@@ -164,22 +164,31 @@ def test_reduced_precision_errors(sim_mod, references, name, storage):
     assert edq_avg <= TOL_DQ[(storage, name)]  # and on the time average
 
 
-def test_f16_dq_mean_over_realizations_shear256(sim_mod, references):
-    """On the 256^2 shear one F16 run leaves the a3_F dq mode with a random
-    error of about 17% (one standard deviation): the rounding is unbiased, so
-    the mean over independent realizations converges to FP64's value."""
-    wl = WORKLOADS["shear256"]
-    ref_avg = references["shear256"][2]
+# realizations, bar on the error of their mean, bar on their spread (standard
+# deviation of the relative error; measured 14-17% on 256^2, 2.9% on 1024^2)
+REALIZATION_CASES = {"shear256": (32, 0.10, 0.35), "shear1024": (12, 0.05, 0.08)}
+
+
+@pytest.mark.parametrize("name", list(REALIZATION_CASES))
+def test_f16_dq_over_realizations(sim_mod, references, name):
+    """The rounding noise of the F16 a3_F dq mode, measured over independent
+    stochastic-rounding realizations: the rounding is unbiased (the mean over
+    realizations converges to FP64's value) and its spread stays at the
+    documented budget (one run on 256^2 scatters by about 17%, on 1024^2 by
+    about 3%)."""
+    count, tol_mean, tol_std = REALIZATION_CASES[name]
+    wl = WORKLOADS[name]
+    ref_avg = references[name][2]
     ka = int(np.argmax(np.abs(ref_avg)))
     vals = []
-    for k in range(REALIZATIONS):
+    for k in range(count):
         _, _, a4 = run(sim_mod, wl(4), "f16dev", 4, offset=k * OFFSET)
         _, _, a2 = run(sim_mod, wl(2), "f16dev", 2, offset=k * OFFSET)
         vals.append((a2 - a4)[ka])
     rel = (np.array(vals) - ref_avg[ka]) / abs(ref_avg[ka])
     err_mean = abs(np.mean(vals) - ref_avg[ka]) / abs(ref_avg[ka])
-    print("shear256 f16dev, %d realizations: dq mode error mean %+.4f (of the mean %.4f), "
-          "std %.4f, max %.3f" % (REALIZATIONS, rel.mean(), err_mean, rel.std(ddof=1),
+    print("%s f16dev, %d realizations: dq mode error mean %+.4f (of the mean %.4f), "
+          "std %.4f, max %.3f" % (name, count, rel.mean(), err_mean, rel.std(ddof=1),
                                   np.abs(rel).max()), flush=True)
-    assert err_mean <= 0.10
-    assert rel.std(ddof=1) <= 0.35
+    assert err_mean <= tol_mean
+    assert rel.std(ddof=1) <= tol_std
